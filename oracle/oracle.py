@@ -1,0 +1,274 @@
+"""ctypes wrapper of the CPU oracle (``mmoc_oracle.c``).
+
+TEST INFRASTRUCTURE: only the test-suite, the smoke check and the benchmark's
+CPU-baseline leg import this module.  The GPU library never does.
+
+Arrays follow the oracle's C conventions: fields are structure-of-arrays
+``[ncomp][N]`` float64 in the oracle's unique DoF order (macro-major, first
+occurrence, nodes of a macro in lexicographic lattice order).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = [os.path.join(HERE, "mmoc_oracle.c"), os.path.join(HERE, "mlp_oracle.c")]
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+_lock = threading.Lock()
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction)."""
+    srcs = [s for s in SRC if os.path.exists(s)]
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
+               "-Wno-unused-function", "-shared", "-fPIC", "-o", tmp] + srcs + ["-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB) or any(os.path.getmtime(s) > os.path.getmtime(LIB)
+                                              for s in SRC if os.path.exists(s)):
+                build(force=True)
+            L = C.CDLL(LIB)
+            P = C.c_void_p
+            dp = C.POINTER(C.c_double)
+            ip = C.POINTER(C.c_int32)
+            lp = C.POINTER(C.c_int64)
+            L.orc_mesh_new.restype = P
+            L.orc_mesh_new.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_int, ip, C.c_int]
+            L.orc_mesh_free.argtypes = [P]
+            L.orc_num_dofs.restype = C.c_int64
+            L.orc_num_dofs.argtypes = [P]
+            L.orc_nodes_per_macro.restype = C.c_int64
+            L.orc_nodes_per_macro.argtypes = [P]
+            L.orc_lat_idx.restype = C.c_int64
+            L.orc_lat_idx.argtypes = [C.c_int] * 4
+            L.orc_macro_geometry.argtypes = [P, C.c_int, dp, dp, dp, ip]
+            L.orc_plane.argtypes = [P, C.c_int, dp, dp]
+            L.orc_dof_coords.argtypes = [P, dp]
+            L.orc_dof_owner.argtypes = [P, ip, ip]
+            L.orc_slot_uids.argtypes = [P, ip]
+            L.orc_bary.argtypes = [P, C.c_int, dp, dp]
+            L.orc_brute.restype = C.c_int
+            L.orc_brute.argtypes = [P, dp]
+            L.orc_walk.restype = C.c_int
+            L.orc_walk.argtypes = [P, C.c_int, dp, C.c_int, C.POINTER(C.c_int)]
+            L.orc_micro_simplex.argtypes = [P, C.c_int, dp, ip, dp]
+            L.orc_eval.argtypes = [P, C.c_int, dp, C.c_int64, dp, ip, C.c_int, dp, ip, ip]
+            L.orc_trace.restype = C.c_int
+            L.orc_trace.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_int64, lp,
+                                    dp, dp, lp]
+            L.orc_p2_mass_ref.argtypes = [C.c_int, dp]
+            L.orc_micro_simplices.restype = C.c_int64
+            L.orc_micro_simplices.argtypes = [P, ip, C.c_int64]
+            L.orc_mass_quadform.restype = C.c_double
+            L.orc_mass_quadform.argtypes = [P, dp, dp]
+            if hasattr(L, "orc_mlp_forward"):
+                _bind_mlp(L)
+            _lib = L
+        return _lib
+
+
+def _bind_mlp(L):
+    dp = C.POINTER(C.c_double)
+    fp = C.POINTER(C.c_float)
+    L.orc_mlp_nparams.restype = C.c_int64
+    L.orc_mlp_nparams.argtypes = []
+    L.orc_mlp_forward.argtypes = [dp, C.c_int64, dp, dp, C.c_int]
+    L.orc_mlp_loss_grad.restype = C.c_double
+    L.orc_mlp_loss_grad.argtypes = [dp, C.c_int64, dp, dp, dp, C.c_int]
+    L.orc_bf16_round.restype = C.c_double
+    L.orc_bf16_round.argtypes = [C.c_double]
+    L.orc_gelu.restype = C.c_double
+    L.orc_gelu.argtypes = [C.c_double]
+    L.orc_adam_step.argtypes = [dp, dp, dp, dp, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                C.c_double, C.c_int64]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _lp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+class Mesh:
+    """Oracle view of a macro mesh refined to ``level``."""
+
+    def __init__(self, dim, level, vertices, macros, blend=0):
+        L = lib()
+        self.dim, self.level, self.blend = int(dim), int(level), int(blend)
+        self.n = 1 << self.level
+        self.m = 2 * self.n
+        self.vertices = np.ascontiguousarray(vertices, dtype=np.float64)
+        self.macros = np.ascontiguousarray(macros, dtype=np.int32)
+        self._h = L.orc_mesh_new(self.dim, self.level, self.vertices.shape[0], _dp(self.vertices),
+                                 self.macros.shape[0], _ip(self.macros), self.blend)
+        if not self._h:
+            raise ValueError("oracle rejected the mesh")
+        self.N = int(L.orc_num_dofs(self._h))
+        self.npm = int(L.orc_nodes_per_macro(self._h))
+        self.nm = int(self.macros.shape[0])
+
+    @classmethod
+    def from_workload(cls, wl, level=None):
+        return cls(wl.dim, wl.level if level is None else level, wl.vertices, wl.macros, wl.blend)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.orc_mesh_free(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self._h = None
+
+    def dof_coords(self):
+        out = np.empty((self.dim, self.N))
+        lib().orc_dof_coords(self._h, _dp(out))
+        return out
+
+    def dof_owner(self):
+        own = np.empty(self.N, dtype=np.int32)
+        lat = np.empty((self.N, 3), dtype=np.int32)
+        lib().orc_dof_owner(self._h, _ip(own), _ip(lat))
+        return own, lat
+
+    def slot_uids(self):
+        out = np.empty((self.nm, self.npm), dtype=np.int32)
+        lib().orc_slot_uids(self._h, _ip(out))
+        return out
+
+    def geometry(self, M):
+        d = self.dim
+        v0, B, Bi = np.empty(d), np.empty((d, d)), np.empty((d, d))
+        nb = np.empty(d + 1, dtype=np.int32)
+        lib().orc_macro_geometry(self._h, int(M), _dp(v0), _dp(B), _dp(Bi), _ip(nb))
+        return v0, B, Bi, nb
+
+    def plane(self, M):
+        n = np.empty(3)
+        c = np.empty(1)
+        lib().orc_plane(self._h, int(M), _dp(n), _dp(c))
+        return n, float(c[0])
+
+    def bary(self, M, y):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        lam = np.empty(self.dim + 1)
+        lib().orc_bary(self._h, int(M), _dp(y), _dp(lam))
+        return lam
+
+    def brute(self, y):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        return int(lib().orc_brute(self._h, _dp(y)))
+
+    def walk(self, M, y, max_hops=64):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        fl = C.c_int(0)
+        r = lib().orc_walk(self._h, int(M), _dp(y), int(max_hops), C.byref(fl))
+        return int(r), int(fl.value)
+
+    def micro_simplex(self, M, y):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        V = np.zeros((4, 3), dtype=np.int32)
+        mu = np.zeros(4)
+        lib().orc_micro_simplex(self._h, int(M), _dp(y), _ip(V), _dp(mu))
+        return V[: self.dim + 1, : self.dim], mu[: self.dim + 1]
+
+    def micro_simplices(self):
+        cnt = int(lib().orc_micro_simplices(self._h, None, 0))
+        V = np.zeros((cnt, 4, 3), dtype=np.int32)
+        lib().orc_micro_simplices(self._h, _ip(V), cnt)
+        return V[:, : self.dim + 1, : self.dim]
+
+    def eval(self, field, pts, start=None, max_hops=64):
+        """Evaluate P2 field(s) ``[ncomp][N]`` (or ``[N]``) at points ``[npts][dim]``."""
+        f = np.ascontiguousarray(np.atleast_2d(field), dtype=np.float64)
+        ncomp = f.shape[0]
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, self.dim)
+        npts = pts.shape[0]
+        out = np.empty((npts, ncomp))
+        mac = np.empty(npts, dtype=np.int32)
+        fl = np.empty(npts, dtype=np.int32)
+        st = None
+        if start is not None:
+            st = np.ascontiguousarray(np.broadcast_to(np.asarray(start, dtype=np.int32), (npts,)))
+        lib().orc_eval(self._h, ncomp, _dp(f), npts, _dp(pts), _ip(st) if st is not None else None,
+                       int(max_hops), _dp(out), _ip(mac), _ip(fl))
+        return out, mac, fl
+
+    def trace(self, u0, u1, c, dt, substeps, ids=None, max_hops=64, threads=1):
+        """One advection step; returns (chat [n], X [dim][n], stats [4])."""
+        u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(self.dim, self.N)
+        u1 = None if u1 is None else np.ascontiguousarray(u1, dtype=np.float64).reshape(self.dim, self.N)
+        c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.N)
+        if ids is None:
+            ids_arr = np.arange(self.N, dtype=np.int64)
+        else:
+            ids_arr = np.ascontiguousarray(ids, dtype=np.int64)
+        n = ids_arr.shape[0]
+        chat = np.empty(n)
+        X = np.empty((self.dim, n))
+        stats = np.zeros(4, dtype=np.int64)
+        L = lib()
+
+        def run(lo, hi, st):
+            sub_ids = np.ascontiguousarray(ids_arr[lo:hi])
+            ch = np.empty(hi - lo)
+            Xs = np.empty((self.dim, hi - lo))
+            r = L.orc_trace(self._h, _dp(u0), _dp(u1) if u1 is not None else None, _dp(c),
+                            float(dt), int(substeps), int(max_hops), hi - lo, _lp(sub_ids),
+                            _dp(ch), _dp(Xs), _lp(st))
+            if r != 0:
+                raise ValueError("oracle trace rejected its arguments")
+            chat[lo:hi] = ch
+            X[:, lo:hi] = Xs
+
+        if threads <= 1 or n < 2 * threads:
+            run(0, n, stats)
+        else:
+            bounds = np.linspace(0, n, threads + 1).astype(np.int64)
+            sts = [np.zeros(4, dtype=np.int64) for _ in range(threads)]
+            ths = [threading.Thread(target=run, args=(int(bounds[k]), int(bounds[k + 1]), sts[k]))
+                   for k in range(threads)]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+            stats = sum(sts)
+        return chat, X, stats
+
+    def mass_quadform(self, a, b):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        return float(lib().orc_mass_quadform(self._h, _dp(a), _dp(b)))
+
+
+def p2_mass_ref(dim):
+    nb = (dim + 1) * (dim + 2) // 2
+    out = np.empty((nb, nb))
+    lib().orc_p2_mass_ref(int(dim), _dp(out))
+    return out
+
+
+def lat_idx(dim, I, J, K=0):
+    return int(lib().orc_lat_idx(int(dim), int(I), int(J), int(K)))
