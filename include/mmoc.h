@@ -1,0 +1,222 @@
+/*
+ * mmoc.h -- C-ABI of the MI355X particle tracer for the modified method of
+ * characteristics (MMOC) on block-structured P2 meshes.
+ *
+ * One call of mmoc_trace_step performs the Lagrangian part of one advection
+ * time step (Alg. 1, departure-point and advection lines; Sec. 2.3.1 steps
+ * (i)-(iii)):
+ *   (i)   a particle is created at every P2 degree of freedom x_i (vertices
+ *         and edge midpoints of the macro mesh refined `level` times);
+ *   (ii)  it is traced backwards over [t_n, t_{n+1}] with RK4 (Sec. 3.1) in
+ *         `substeps` sub-steps, the velocity being linear in time between the
+ *         two levels u_h^n and u_h^{n+1} (eq. linear-interpolation), giving the
+ *         departure point X_i (eq. departure-point);
+ *   (iii) the scalar c_h^n is evaluated at X_i: chat_i = c_h^n(X_i)
+ *         (eq. mmoc-approximation).
+ * Every field evaluation locates the point first in a macro element, by a
+ * walk from the macro of the previous evaluation, and then in a micro
+ * element in O(1) (Sec. 2.3.2), and sums the P2 shape functions.
+ *
+ * Conventions
+ *  - All functions return an mmoc_status; MMOC_OK == 0, errors are negative.
+ *    On error nothing has been enqueued on the stream and mmoc_last_error()
+ *    holds a one-line reason.  No C++ exception crosses this interface.
+ *  - Device pointers ("_dev") must be device memory of the context's GPU,
+ *    8-byte aligned for double and 4-byte aligned for float; the library
+ *    checks both (hipPointerGetAttributes) and never frees caller memory.
+ *  - All device work is enqueued on the stream given at creation (or by
+ *    mmoc_set_stream); calls return before the work has finished.  Outputs
+ *    are valid once that stream is synchronised.  mmoc_get_stats
+ *    synchronises the stream.
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - Unique DoF order ("unique layout"): macro-major, each DoF at its first
+ *    occurrence; inside a macro, lattice nodes (I, J, K), m >= I >= J >= K
+ *    >= 0, m = 2^(level+1), in lexicographic order.  A DoF on an interface
+ *    belongs to the lowest-index macro that contains it (the paper leaves the
+ *    choice open, Sec. 2.3.1 step (i)).  mmoc_dof_coords returns positions in
+ *    this order.
+ *  - Vector fields are structure-of-arrays [dim][n_unique] float64.
+ */
+#ifndef MMOC_H
+#define MMOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mmoc_ctx mmoc_ctx; /* opaque; owned by the library */
+
+typedef enum {
+    MMOC_OK = 0,
+    MMOC_E_ARG = -1,         /* invalid argument (null/misaligned/host pointer, size, value) */
+    MMOC_E_MESH = -2,        /* invalid mesh (degenerate, non-manifold, non-conforming order) */
+    MMOC_E_STATE = -3,       /* call out of order (e.g. trace before fields are set) */
+    MMOC_E_HIP = -4,         /* HIP runtime error */
+    MMOC_E_NOMEM = -5,       /* device allocation failed */
+    MMOC_E_UNSUPPORTED = -6  /* combination not built (e.g. 2D shell blending) */
+} mmoc_status;
+
+typedef enum {
+    MMOC_FP64 = 0,       /* every stage in float64 */
+    MMOC_FP32_MIXED = 1  /* stages, location and interpolation in float32 on float32 field
+                            copies; location decisions within eps of a macro or micro face
+                            re-taken in float64; departure points accumulated in float64 */
+} mmoc_precision;
+
+typedef enum {
+    MMOC_BLEND_NONE = 0,         /* physical domain = computational domain */
+    MMOC_BLEND_SHELL_RADIAL = 1  /* spherical shell: each macro's column (its three unit
+                                    directions span a plane n.x = c) is mapped radially,
+                                    Phi(x) = x (n.x)/(c|x|) (Sec. 2.1 blending function) */
+} mmoc_blend;
+
+typedef struct {
+    double eps_in;     /* macro acceptance: min barycentric >= -eps_in (default 1e-12) */
+    float eps32_macro; /* FP32 path: macro decisions with |min lambda| < eps redone in FP64 (4e-6) */
+    float eps32_micro; /* FP32 path: micro decisions with a sorted-coordinate gap < eps*n
+                          redone in FP64 (2^-17) */
+    int max_hops;      /* walk hops before brute-force location (default 64) */
+    int reserved[4];
+} mmoc_options;
+
+typedef struct {
+    int64_t n_particles;   /* particles traced since the last reset */
+    int64_t n_outside;     /* particles with at least one evaluation outside the domain
+                              (extrapolated from the boundary element) */
+    int64_t n_multi_hop;   /* particles whose walk needed more than one hop at least once */
+    int64_t n_bruteforce;  /* particles located by brute force at least once */
+    int64_t n_tieband;     /* FP32 path: particles with at least one FP64 tie-break */
+    int64_t n_nan;         /* particles with a NaN departure point or value */
+    int64_t n_checked;     /* surrogate: particles re-traced by RK4 as the check sample */
+    int64_t n_fallback;    /* surrogate: particles whose result came from the RK4 fallback */
+    double max_check_residual; /* surrogate: largest |Xhat - X_rk4|_inf over the check sample */
+} mmoc_stats;
+
+/* Fills *opt with the defaults listed above. */
+void mmoc_default_options(mmoc_options* opt);
+
+/* Creates a context for a mesh of dimension dim (2: triangles, 3: tetrahedra)
+ * whose macros are refined `level` times (0..10 in 2D, 0..9 in 3D).  opt may be NULL
+ * (defaults).  hip_stream is a hipStream_t (NULL: the null stream).  Selects
+ * the current HIP device.  *out is NULL on failure. */
+mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec,
+                        const mmoc_options* opt, void* hip_stream);
+
+/* Changes the stream used by later calls. */
+mmoc_status mmoc_set_stream(mmoc_ctx* ctx, void* hip_stream);
+
+/* Uploads the coarse mesh (Sec. 2.1: the macro elements that are refined
+ * uniformly; Sec. 2.3.1 grid data structure).  vertex_xyz: host [n_vertices][dim]
+ * computational-domain coordinates; macro_vertices: host [n_macros][dim+1]
+ * vertex ids.  Macros sharing a face must list the face's vertices in the same
+ * relative order (this makes the refined meshes conform; ascending ids always
+ * do).  Derives face neighbours, the unique DoF numbering and the per-macro
+ * block layout, and uploads them.  May be called once per context.
+ * Errors: MMOC_E_MESH for degenerate or non-manifold meshes or non-conforming
+ * vertex orders, MMOC_E_UNSUPPORTED for shell blending with dim != 3. */
+mmoc_status mmoc_upload_mesh(mmoc_ctx* ctx, int n_vertices, const double* vertex_xyz,
+                             int n_macros, const int32_t* macro_vertices, mmoc_blend blend);
+
+/* Number of unique DoFs (= particles) and of block-layout slots (duplicated
+ * interface nodes included). */
+mmoc_status mmoc_num_dofs(const mmoc_ctx* ctx, int64_t* n_unique, int64_t* n_block);
+
+/* Writes the physical DoF positions x_i, SoA [dim][n_unique] float64, device
+ * memory owned by the caller (Sec. 2.3.1 step (i)). */
+mmoc_status mmoc_dof_coords(mmoc_ctx* ctx, double* xyz_dev);
+
+/* Sets velocity level 0 (u_h^n at t_n) or 1 (u_h^{n+1} at t_{n+1}) from a
+ * unique-layout SoA [dim][n_unique] float64 device array (eq.
+ * linear-interpolation).  The values are copied into the library's block
+ * layout (float32 for MMOC_FP32_MIXED); the caller may free u_dev once the
+ * stream has passed this call. */
+mmoc_status mmoc_set_velocity(mmoc_ctx* ctx, int level, const double* u_dev);
+
+/* on != 0: the velocity is stationary; only level 0 is used (level 1 need not
+ * be set) and each stage evaluates one field. */
+mmoc_status mmoc_set_stationary(mmoc_ctx* ctx, int on);
+
+/* Makes level 1 the new level 0 (u^{n+1} becomes u^n for the next step, no
+ * copy).  Level 1 and the scalar must be set again before the next trace. */
+mmoc_status mmoc_swap_velocity_levels(mmoc_ctx* ctx);
+
+/* Sets the scalar c_h^n from a unique-layout [n_unique] float64 device array
+ * (copied into the block layout). */
+mmoc_status mmoc_set_scalar(mmoc_ctx* ctx, const double* c_dev);
+
+/* One MMOC advection step of length dt > 0 with substeps >= 1 RK4 sub-steps
+ * (Alg. 1 departure-point and advection lines).  c_hat_dev receives
+ * chat_i = c_h^n(X_i) in unique order: double* [n_unique] for MMOC_FP64,
+ * float* [n_unique] for MMOC_FP32_MIXED.  X_dev (may be NULL) receives the
+ * departure points, SoA [dim][n_unique] float64 (physical coordinates).
+ * Points that leave the domain are evaluated by extrapolating the boundary
+ * element reached by the walk (counted in n_outside). */
+mmoc_status mmoc_trace_step(mmoc_ctx* ctx, double dt, int substeps, void* c_hat_dev, double* X_dev);
+
+/* Statistics accumulated since creation or the last reset; synchronises. */
+mmoc_status mmoc_get_stats(mmoc_ctx* ctx, mmoc_stats* out);
+mmoc_status mmoc_reset_stats(mmoc_ctx* ctx);
+
+/* ---------------- learned flow-map surrogate (not part of the paper) -------
+ * An MLP (x, t_{n+1}) -> scaled displacement, 4 -> 64 -> 64 -> 64 -> 3 with
+ * tanh-form GELU (Hendrycks & Gimpel 2016), bf16 weights and activations,
+ * fp32 accumulation on the matrix cores.  Inputs are affinely scaled to
+ * [-1,1] (box [lo, hi] per input), the output is (X - x) / (dt * U).
+ * Parameters are a flat float32 vector of mmoc_mlp_nparams() entries, layer
+ * by layer: W1 [64][4], b1 [64], W2 [64][64], b2 [64], W3 [64][64], b3 [64],
+ * W4 [3][64], b4 [3] (W[out][in]). */
+
+int64_t mmoc_mlp_nparams(void);
+
+/* Input box: lo[4], hi[4] for (x, y, z, t); output scale U > 0. */
+mmoc_status mmoc_mlp_configure(mmoc_ctx* ctx, const double* lo, const double* hi, double U);
+
+/* Appends training pairs: the current DoF positions with time t_np1 as
+ * inputs and X_dev (SoA [dim][n_unique] float64, a step of length dt) as
+ * targets.  Buffers up to `capacity` pairs (set by the first call; library
+ * owned device memory). */
+mmoc_status mmoc_mlp_record(mmoc_ctx* ctx, double t_np1, double dt, const double* X_dev,
+                            int64_t capacity);
+
+/* Trains on `n_samples` pairs drawn (seeded, with replacement) from the
+ * recorded ones: `epochs` passes of n_samples/batch Adam steps (beta 0.9,
+ * 0.999, eps 1e-8), learning rate cosine-decayed from lr to lr/100, MSE
+ * loss.  Forward and backward run on the GPU (bf16 matrix cores, fp32
+ * master weights and moments).  *final_loss receives the mean loss of the
+ * last epoch (may be NULL); synchronises. */
+mmoc_status mmoc_mlp_train(mmoc_ctx* ctx, int64_t n_samples, int epochs, int batch, float lr,
+                           unsigned long long seed, double* final_loss);
+
+/* Host float32 copies of the master parameters. */
+mmoc_status mmoc_mlp_get_weights(mmoc_ctx* ctx, float* host_params, int64_t n);
+mmoc_status mmoc_mlp_set_weights(mmoc_ctx* ctx, const float* host_params, int64_t n);
+
+/* Surrogate inference for all particles: Xhat_i = x_i + dt U MLP(x_i, t_np1),
+ * written to X_dev (SoA [dim][n_unique] float64). */
+mmoc_status mmoc_mlp_infer(mmoc_ctx* ctx, double t_np1, double dt, double* X_dev);
+
+/* Surrogate step: inference for all particles, then an RK4 re-trace (FP32
+ * mixed tracer, same fields) of a seeded sample of about check_fraction of
+ * the particles (hash(seed, step, i) < check_fraction, with at least one per
+ * tile of 128 particles); a checked particle with residual
+ * |Xhat - X_rk4|_inf > tol takes its RK4 result, and every particle of a tile
+ * in which some checked residual exceeds tol/2 is re-traced by RK4 (fallback).
+ * Then chat = c_h^n(X) as in mmoc_trace_step.  c_hat_dev: double* for
+ * MMOC_FP64 contexts, float* for MMOC_FP32_MIXED.  step seeds the sample. */
+mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* ctx, double t_np1, double dt, int substeps,
+                                      float check_fraction, double tol, int64_t step,
+                                      void* c_hat_dev, double* X_dev);
+
+/* Reason of the last failed call on ctx (valid until the next call). */
+const char* mmoc_last_error(const mmoc_ctx* ctx);
+
+/* Frees the context and all library-owned device memory (synchronises). */
+void mmoc_destroy(mmoc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMOC_H */

@@ -1,0 +1,628 @@
+// mmoc_host.cpp -- host side of the MMOC tracer library: the C-ABI declared
+// in include/mmoc.h, argument and mesh validation, the coarse-mesh tables and
+// the unique DoF numbering (Sec. 2.1 and Sec. 2.3.1 grid data structure).
+//
+// Unique numbering.  Every sub-simplex (vertex, edge, face) of the coarse
+// mesh is owned by the lowest-index macro that contains it; a lattice node
+// is owned by the owner of the smallest sub-simplex that carries it (its
+// support: the macro vertices with nonzero barycentric weight).  Walking the
+// macros in index order and their nodes in lexicographic (I, J, K) order, a
+// node gets the next unique index in its owner; elsewhere it takes the index
+// of the same node in the owner, found by re-expressing its barycentric
+// weights in the owner's vertex order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mmoc.h"
+#include "mmoc_internal.h"
+
+using mmoc::MacroGeo;
+
+struct mmoc_ctx {
+    int dim = 0, level = 0, n = 0, m = 0;
+    mmoc_precision prec = MMOC_FP64;
+    mmoc_options opt{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+
+    bool mesh_ok = false;
+    int blend = 0;
+    int nm = 0;
+    int64_t npm = 0, nslots = 0, N = 0;
+    MacroGeo* geo_d = nullptr;
+    uint64_t* owned_d = nullptr;
+    int32_t* slot_uid_d = nullptr;
+    void* rec_d[2] = {nullptr, nullptr};
+    bool vel_set[2] = {false, false};
+    bool scalar_set = false;
+    bool stationary = false;
+    unsigned long long* stats_d = nullptr;
+
+    struct mlp_state* mlp = nullptr;
+};
+
+namespace {
+
+mmoc_status fail(mmoc_ctx* c, mmoc_status st, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return st;
+}
+
+mmoc_status hip_fail(mmoc_ctx* c, hipError_t e, const char* what)
+{
+    return fail(c, e == hipErrorOutOfMemory ? MMOC_E_NOMEM : MMOC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call, what)                   \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+// A device pointer must be device memory of the context's GPU, aligned, and
+// its allocation must hold `bytes` from p on.
+mmoc_status check_dev(mmoc_ctx* c, const void* p, size_t bytes, size_t align, const char* name)
+{
+    if (!p) return fail(c, MMOC_E_ARG, "%s is null", name);
+    if (reinterpret_cast<uintptr_t>(p) % align) return fail(c, MMOC_E_ARG, "%s is not %zu-byte aligned", name, align);
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, MMOC_E_ARG, "%s is not a device pointer", name);
+    }
+    if (at.type != hipMemoryTypeDevice) return fail(c, MMOC_E_ARG, "%s is not device memory", name);
+    if (at.device != c->device) return fail(c, MMOC_E_ARG, "%s lives on device %d, context on %d", name, at.device, c->device);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, MMOC_E_ARG, "%s: allocation range unknown", name);
+    }
+    const char* b = reinterpret_cast<const char*>(base);
+    const char* q = reinterpret_cast<const char*>(p);
+    if (q < b || (size_t)(q - b) + bytes > size)
+        return fail(c, MMOC_E_ARG, "%s: allocation too small (%zu bytes needed from this address)", name, bytes);
+    return MMOC_OK;
+}
+
+template <typename T>
+mmoc_status dev_alloc(mmoc_ctx* c, T** p, size_t count, const char* what)
+{
+    *p = nullptr;
+    if (count == 0) return MMOC_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(c, e, what);
+    }
+    return MMOC_OK;
+}
+
+int64_t lattice_count(int dim, int m)
+{
+    return dim == 2 ? (int64_t)(m + 1) * (m + 2) / 2 : (int64_t)(m + 1) * (m + 2) * (m + 3) / 6;
+}
+
+int64_t lattice_index(int dim, int64_t I, int64_t J, int64_t K)
+{
+    return dim == 2 ? I * (I + 1) / 2 + J : I * (I + 1) * (I + 2) / 6 + J * (J + 1) / 2 + K;
+}
+
+// d x d inverse by cofactors; returns determinant
+double invert(int d, const double* B, double* Bi)
+{
+    if (d == 2) {
+        const double det = B[0] * B[3] - B[1] * B[2];
+        Bi[0] = B[3] / det;
+        Bi[1] = -B[1] / det;
+        Bi[2] = -B[2] / det;
+        Bi[3] = B[0] / det;
+        return det;
+    }
+    double C[9];
+    C[0] = B[4] * B[8] - B[5] * B[7];
+    C[1] = B[5] * B[6] - B[3] * B[8];
+    C[2] = B[3] * B[7] - B[4] * B[6];
+    C[3] = B[2] * B[7] - B[1] * B[8];
+    C[4] = B[0] * B[8] - B[2] * B[6];
+    C[5] = B[1] * B[6] - B[0] * B[7];
+    C[6] = B[1] * B[5] - B[2] * B[4];
+    C[7] = B[2] * B[3] - B[0] * B[5];
+    C[8] = B[0] * B[4] - B[1] * B[3];
+    const double det = B[0] * C[0] + B[1] * C[1] + B[2] * C[2];
+    // inverse = adj / det, adj[r][c] = C[c][r]
+    for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) Bi[r * 3 + cc] = C[cc * 3 + r] / det;
+    return det;
+}
+
+void free_all(mmoc_ctx* c);
+
+}  // namespace
+
+// surrogate state is defined in mmoc_mlp.cpp
+void mmoc_mlp_free_state(mmoc_ctx* c);
+
+extern "C" {
+
+void mmoc_default_options(mmoc_options* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->eps_in = 1e-12;
+    o->eps32_macro = 4e-6f;
+    o->eps32_micro = 1.0f / 131072.0f;
+    o->max_hops = 64;
+}
+
+mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec, const mmoc_options* opt,
+                        void* hip_stream)
+{
+    if (!out) return MMOC_E_ARG;
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return MMOC_E_ARG;
+    if (level < 0 || level > 10 || (dim == 3 && level > 9)) return MMOC_E_ARG;  // lattice index fits int32
+    if (prec != MMOC_FP64 && prec != MMOC_FP32_MIXED) return MMOC_E_ARG;
+    if (opt && (!(opt->eps_in >= 0) || opt->max_hops < 0 || !(opt->eps32_macro >= 0) || !(opt->eps32_micro >= 0)))
+        return MMOC_E_ARG;
+    mmoc_ctx* c = new (std::nothrow) mmoc_ctx();
+    if (!c) return MMOC_E_NOMEM;
+    c->dim = dim;
+    c->level = level;
+    c->n = 1 << level;
+    c->m = 2 * c->n;
+    c->prec = prec;
+    if (opt) c->opt = *opt;
+    else mmoc_default_options(&c->opt);
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return MMOC_E_HIP;
+    }
+    if (dev_alloc(c, &c->stats_d, mmoc::ST_COUNT, "stats") != MMOC_OK ||
+        hipMemset(c->stats_d, 0, sizeof(unsigned long long) * mmoc::ST_COUNT) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return MMOC_E_HIP;
+    }
+    *out = c;
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_set_stream(mmoc_ctx* c, void* hip_stream)
+{
+    if (!c) return MMOC_E_ARG;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, const int32_t* mv, mmoc_blend blend)
+{
+    if (!c) return MMOC_E_ARG;
+    if (c->mesh_ok) return fail(c, MMOC_E_STATE, "mesh already uploaded");
+    if (!vert || !mv || nv <= 0 || nm <= 0) return fail(c, MMOC_E_ARG, "empty mesh or null array");
+    if (blend != MMOC_BLEND_NONE && blend != MMOC_BLEND_SHELL_RADIAL) return fail(c, MMOC_E_ARG, "unknown blend");
+    if (blend == MMOC_BLEND_SHELL_RADIAL && c->dim != 3) return fail(c, MMOC_E_UNSUPPORTED, "shell blending needs dim 3");
+    const int d = c->dim, nvm = d + 1;
+    if (nm >= (1 << 27)) return fail(c, MMOC_E_ARG, "too many macros");
+    const int64_t npm = lattice_count(d, c->m);
+    if ((int64_t)nm * npm >= (int64_t)INT32_MAX) return fail(c, MMOC_E_ARG, "mesh too large for 32-bit slot indices");
+    for (int i = 0; i < nv * d; ++i)
+        if (!std::isfinite(vert[i])) return fail(c, MMOC_E_MESH, "vertex coordinate %d is not finite", i);
+    for (int M = 0; M < nm; ++M)
+        for (int a = 0; a < nvm; ++a) {
+            const int v = mv[M * nvm + a];
+            if (v < 0 || v >= nv) return fail(c, MMOC_E_MESH, "macro %d vertex %d out of range", M, a);
+            for (int b = 0; b < a; ++b)
+                if (mv[M * nvm + b] == v) return fail(c, MMOC_E_MESH, "macro %d repeats vertex %d", M, v);
+        }
+
+    // --- geometry
+    std::vector<MacroGeo> geo(nm);
+    for (int M = 0; M < nm; ++M) {
+        MacroGeo& G = geo[M];
+        std::memset(&G, 0, sizeof G);
+        const double* p0 = vert + (size_t)mv[M * nvm] * d;
+        double B[9] = {0}, Bi[9] = {0}, scale = 0;
+        for (int i = 0; i < d; ++i) G.v0[i] = p0[i];
+        for (int a = 0; a < d; ++a) {
+            const double* pa = vert + (size_t)mv[M * nvm + a + 1] * d;
+            for (int i = 0; i < d; ++i) {
+                B[i * d + a] = pa[i] - p0[i];
+                scale = std::max(scale, std::fabs(B[i * d + a]));
+            }
+        }
+        const double det = invert(d, B, Bi);
+        if (!(std::fabs(det) > 1e-12 * std::pow(scale, d)))
+            return fail(c, MMOC_E_MESH, "macro %d is degenerate (det %.3g)", M, det);
+        for (int r = 0; r < d; ++r)
+            for (int q = 0; q < d; ++q) {
+                G.B[r * 3 + q] = B[r * d + q];
+                G.binv[r * 3 + q] = Bi[r * d + q];
+                G.binvf[r * 3 + q] = (float)Bi[r * d + q];
+            }
+        if (blend == MMOC_BLEND_SHELL_RADIAL) {
+            // plane through the macro's three unit directions: n' with n'.d_k = 1
+            double dirs[3][3];
+            int nd = 0;
+            for (int a = 0; a < 4; ++a) {
+                const double* p = vert + (size_t)mv[M * 4 + a] * 3;
+                const double r = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+                if (!(r > 0)) return fail(c, MMOC_E_MESH, "shell vertex at the origin");
+                const double q[3] = {p[0] / r, p[1] / r, p[2] / r};
+                bool dup = false;
+                for (int b = 0; b < nd; ++b)
+                    dup |= std::fabs(q[0] - dirs[b][0]) + std::fabs(q[1] - dirs[b][1]) + std::fabs(q[2] - dirs[b][2]) < 1e-9;
+                if (!dup) {
+                    if (nd == 3) return fail(c, MMOC_E_MESH, "macro %d spans more than three radial directions", M);
+                    std::memcpy(dirs[nd++], q, sizeof q);
+                }
+            }
+            if (nd != 3) return fail(c, MMOC_E_MESH, "macro %d spans fewer than three radial directions", M);
+            double D[9], Di[9];
+            for (int r = 0; r < 3; ++r)
+                for (int q = 0; q < 3; ++q) D[r * 3 + q] = dirs[r][q];  // rows: directions
+            const double dd = invert(3, D, Di);
+            if (!(std::fabs(dd) > 1e-14)) return fail(c, MMOC_E_MESH, "macro %d has a flat column", M);
+            double np[3];
+            for (int r = 0; r < 3; ++r) np[r] = Di[r * 3 + 0] + Di[r * 3 + 1] + Di[r * 3 + 2];  // D n' = 1
+            const double len = std::sqrt(np[0] * np[0] + np[1] * np[1] + np[2] * np[2]);
+            for (int r = 0; r < 3; ++r) G.pn[r] = np[r] / len;
+            G.pc = 1.0 / len;
+        }
+    }
+
+    // --- faces: neighbours, manifoldness, conforming vertex order
+    struct Face {
+        std::array<int32_t, 3> key;
+        int M, k;
+    };
+    std::vector<Face> faces;
+    faces.reserve((size_t)nm * nvm);
+    for (int M = 0; M < nm; ++M)
+        for (int k = 0; k < nvm; ++k) {
+            Face f{{-1, -1, -1}, M, k};
+            int q = 0;
+            for (int a = 0; a < nvm; ++a)
+                if (a != k) f.key[q++] = mv[M * nvm + a];
+            std::sort(f.key.begin(), f.key.begin() + d);
+            faces.push_back(f);
+        }
+    std::sort(faces.begin(), faces.end(), [](const Face& a, const Face& b) {
+        return a.key != b.key ? a.key < b.key : a.M < b.M;
+    });
+    for (int M = 0; M < nm; ++M)
+        for (int k = 0; k < nvm; ++k) geo[M].nbr[k] = -1;
+    for (size_t i = 0; i < faces.size();) {
+        size_t j = i + 1;
+        while (j < faces.size() && faces[j].key == faces[i].key) ++j;
+        if (j - i > 2) return fail(c, MMOC_E_MESH, "face shared by %zu macros", j - i);
+        if (j - i == 2) {
+            const Face &a = faces[i], &b = faces[i + 1];
+            // the face's vertices in local order must be the same sequence in both macros
+            std::vector<int32_t> sa, sb;
+            for (int q = 0; q < nvm; ++q) {
+                if (q != a.k) sa.push_back(mv[a.M * nvm + q]);
+                if (q != b.k) sb.push_back(mv[b.M * nvm + q]);
+            }
+            if (sa != sb)
+                return fail(c, MMOC_E_MESH, "macros %d and %d order their shared face differently (non-conforming refinement)",
+                            a.M, b.M);
+            geo[a.M].nbr[a.k] = b.M;
+            geo[b.M].nbr[b.k] = a.M;
+        }
+        i = j;
+    }
+
+    // --- owner of every sub-simplex, per macro and vertex subset
+    const int nmask = 1 << nvm;
+    std::map<std::array<int32_t, 4>, int> sub_owner;
+    auto key_of = [&](int M, int mask) {
+        std::array<int32_t, 4> k{{INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX}};
+        int q = 0;
+        for (int a = 0; a < nvm; ++a)
+            if (mask >> a & 1) k[q++] = mv[M * nvm + a];
+        std::sort(k.begin(), k.begin() + q);
+        return k;
+    };
+    for (int M = 0; M < nm; ++M)
+        for (int mask = 1; mask < nmask; ++mask) sub_owner.emplace(key_of(M, mask), M);  // first = lowest M
+    std::vector<int32_t> mask_owner((size_t)nm * nmask);
+    for (int M = 0; M < nm; ++M)
+        for (int mask = 1; mask < nmask; ++mask) mask_owner[(size_t)M * nmask + mask] = sub_owner[key_of(M, mask)];
+
+    // --- unique numbering and block slot map
+    const int m = c->m;
+    std::vector<int32_t> slot_uid((size_t)nm * npm);
+    std::vector<uint64_t> owned;
+    owned.reserve((size_t)nm * npm);
+    int64_t N = 0;
+    for (int M = 0; M < nm; ++M) {
+        int64_t idx = 0;
+        for (int I = 0; I <= m; ++I)
+            for (int J = 0; J <= I; ++J)
+                for (int K = 0; K <= (d == 3 ? J : 0); ++K, ++idx) {
+                    int w[4];
+                    if (d == 2) {
+                        w[0] = m - I; w[1] = I - J; w[2] = J; w[3] = 0;
+                    } else {
+                        w[0] = m - I; w[1] = I - J; w[2] = J - K; w[3] = K;
+                    }
+                    int mask = 0;
+                    for (int a = 0; a < nvm; ++a)
+                        if (w[a]) mask |= 1 << a;
+                    const int Mo = mask_owner[(size_t)M * nmask + mask];
+                    int32_t u;
+                    if (Mo == M) {
+                        u = (int32_t)N++;
+                        owned.push_back(mmoc::pack_owned((uint32_t)M, (uint32_t)I, (uint32_t)J, (uint32_t)K));
+                    } else {
+                        // weights in the owner's local vertex order
+                        int wo[4] = {0, 0, 0, 0};
+                        for (int a = 0; a < nvm; ++a) {
+                            if (!w[a]) continue;
+                            const int g = mv[M * nvm + a];
+                            for (int b = 0; b < nvm; ++b)
+                                if (mv[Mo * nvm + b] == g) wo[b] = w[a];
+                        }
+                        int64_t io;
+                        if (d == 2) io = lattice_index(2, wo[1] + wo[2], wo[2], 0);
+                        else io = lattice_index(3, wo[1] + wo[2] + wo[3], wo[2] + wo[3], wo[3]);
+                        u = slot_uid[(size_t)Mo * npm + io];
+                    }
+                    slot_uid[(size_t)M * npm + idx] = u;
+                }
+    }
+
+    // --- upload
+    c->nm = nm;
+    c->npm = npm;
+    c->nslots = (int64_t)nm * npm;
+    c->N = N;
+    c->blend = blend;
+    mmoc_status st;
+    if ((st = dev_alloc(c, &c->geo_d, nm, "geometry")) != MMOC_OK) return st;
+    if ((st = dev_alloc(c, &c->owned_d, (size_t)N, "particle table")) != MMOC_OK) return st;
+    if ((st = dev_alloc(c, &c->slot_uid_d, (size_t)c->nslots, "slot map")) != MMOC_OK) return st;
+    const size_t elem = c->prec == MMOC_FP64 ? sizeof(double) : sizeof(float);
+    for (int l = 0; l < 2; ++l) {
+        hipError_t e = hipMalloc(&c->rec_d[l], (size_t)c->nslots * 4 * elem);
+        if (e != hipSuccess) return hip_fail(c, e, "field records");
+        HIPCHK(c, hipMemsetAsync(c->rec_d[l], 0, (size_t)c->nslots * 4 * elem, c->stream), "clear records");
+    }
+    HIPCHK(c, hipMemcpyAsync(c->geo_d, geo.data(), sizeof(MacroGeo) * nm, hipMemcpyHostToDevice, c->stream), "upload geometry");
+    HIPCHK(c, hipMemcpyAsync(c->owned_d, owned.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, c->stream), "upload particles");
+    HIPCHK(c, hipMemcpyAsync(c->slot_uid_d, slot_uid.data(), sizeof(int32_t) * c->nslots, hipMemcpyHostToDevice, c->stream),
+           "upload slot map");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "mesh upload");
+    c->mesh_ok = true;
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_num_dofs(const mmoc_ctx* c, int64_t* n_unique, int64_t* n_block)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return MMOC_E_STATE;
+    if (n_unique) *n_unique = c->N;
+    if (n_block) *n_block = c->nslots;
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_dof_coords(mmoc_ctx* c, double* xyz)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    mmoc_status st = check_dev(c, xyz, sizeof(double) * c->dim * c->N, 8, "xyz_dev");
+    if (st != MMOC_OK) return st;
+    HIPCHK(c, mmoc::launch_dof_coords(c->dim, c->blend, c->geo_d, c->owned_d, c->N, c->n, xyz, c->stream), "dof_coords");
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_set_velocity(mmoc_ctx* c, int level, const double* u)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (level != 0 && level != 1) return fail(c, MMOC_E_ARG, "level must be 0 or 1");
+    mmoc_status st = check_dev(c, u, sizeof(double) * c->dim * c->N, 8, "u_dev");
+    if (st != MMOC_OK) return st;
+    HIPCHK(c, mmoc::launch_scatter_vec(c->dim, c->slot_uid_d, c->nslots, u, c->N, c->rec_d[level],
+                                       c->prec == MMOC_FP32_MIXED, c->stream),
+           "set_velocity");
+    c->vel_set[level] = true;
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_set_stationary(mmoc_ctx* c, int on)
+{
+    if (!c) return MMOC_E_ARG;
+    c->stationary = on != 0;
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_swap_velocity_levels(mmoc_ctx* c)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (!c->vel_set[1]) return fail(c, MMOC_E_STATE, "velocity level 1 is not set");
+    std::swap(c->rec_d[0], c->rec_d[1]);
+    c->vel_set[0] = true;
+    c->vel_set[1] = false;
+    c->scalar_set = false;  // the scalar lives in the level-0 records
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    mmoc_status st = check_dev(c, cs, sizeof(double) * c->N, 8, "c_dev");
+    if (st != MMOC_OK) return st;
+    HIPCHK(c, mmoc::launch_scatter_scalar(c->slot_uid_d, c->nslots, cs, c->rec_d[0], c->prec == MMOC_FP32_MIXED, c->stream),
+           "set_scalar");
+    c->scalar_set = true;
+    return MMOC_OK;
+}
+
+}  // extern "C"
+
+// Shared by the plain and the surrogate step: validates and launches the RK4
+// tracer on `n` particles (ids == null: all, in canonical order).
+mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* ids,
+                              int64_t n)
+{
+    const bool f32 = c->prec == MMOC_FP32_MIXED;
+    if (f32) {
+        mmoc::TraceArgs<float> a{};
+        a.geo = c->geo_d;
+        a.owned = c->owned_d;
+        a.rec0 = (const float*)c->rec_d[0];
+        a.rec1 = c->stationary ? nullptr : (const float*)c->rec_d[1];
+        a.n = n;
+        a.xstride = c->N;
+        a.nm = c->nm;
+        a.npm = (int)c->npm;
+        a.nlev = c->stationary ? 1 : 2;
+        a.level_n = c->n;
+        a.substeps = substeps;
+        a.max_hops = c->opt.max_hops;
+        a.dt = dt;
+        a.eps_in = c->opt.eps_in;
+        a.eps32_macro = c->opt.eps32_macro;
+        a.eps32_micro = c->opt.eps32_micro;
+        a.c_hat = (float*)c_hat;
+        a.X = X;
+        a.ids = ids;
+        a.stats = c->stats_d;
+        HIPCHK(c, mmoc::launch_trace_fp32(c->dim, c->blend, a, c->stream), "trace (fp32 mixed)");
+    } else {
+        mmoc::TraceArgs<double> a{};
+        a.geo = c->geo_d;
+        a.owned = c->owned_d;
+        a.rec0 = (const double*)c->rec_d[0];
+        a.rec1 = c->stationary ? nullptr : (const double*)c->rec_d[1];
+        a.n = n;
+        a.xstride = c->N;
+        a.nm = c->nm;
+        a.npm = (int)c->npm;
+        a.nlev = c->stationary ? 1 : 2;
+        a.level_n = c->n;
+        a.substeps = substeps;
+        a.max_hops = c->opt.max_hops;
+        a.dt = dt;
+        a.eps_in = c->opt.eps_in;
+        a.c_hat = (double*)c_hat;
+        a.X = X;
+        a.ids = ids;
+        a.stats = c->stats_d;
+        HIPCHK(c, mmoc::launch_trace_fp64(c->dim, c->blend, a, c->stream), "trace (fp64)");
+    }
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_check_step_args(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X)
+{
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (!c->vel_set[0]) return fail(c, MMOC_E_STATE, "velocity level 0 is not set");
+    if (!c->stationary && !c->vel_set[1]) return fail(c, MMOC_E_STATE, "velocity level 1 is not set (or set stationary)");
+    if (!c->scalar_set) return fail(c, MMOC_E_STATE, "scalar is not set");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, MMOC_E_ARG, "dt must be positive and finite");
+    if (substeps < 1 || substeps > (1 << 20)) return fail(c, MMOC_E_ARG, "substeps must be in [1, 2^20]");
+    const size_t es = c->prec == MMOC_FP32_MIXED ? sizeof(float) : sizeof(double);
+    mmoc_status st = check_dev(c, c_hat, es * c->N, es, "c_hat_dev");
+    if (st != MMOC_OK) return st;
+    if (X && (st = check_dev(c, X, sizeof(double) * c->dim * c->N, 8, "X_dev")) != MMOC_OK) return st;
+    return MMOC_OK;
+}
+
+extern "C" {
+
+mmoc_status mmoc_trace_step(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X)
+{
+    if (!c) return MMOC_E_ARG;
+    mmoc_status st = mmoc_check_step_args(c, dt, substeps, c_hat, X);
+    if (st != MMOC_OK) return st;
+    return mmoc_launch_trace(c, dt, substeps, c_hat, X, nullptr, c->N);
+}
+
+mmoc_status mmoc_get_stats(mmoc_ctx* c, mmoc_stats* out)
+{
+    if (!c || !out) return MMOC_E_ARG;
+    unsigned long long h[mmoc::ST_COUNT];
+    HIPCHK(c, hipMemcpyAsync(h, c->stats_d, sizeof h, hipMemcpyDeviceToHost, c->stream), "read stats");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "read stats");
+    out->n_particles = (int64_t)h[mmoc::ST_PARTICLES];
+    out->n_outside = (int64_t)h[mmoc::ST_OUTSIDE];
+    out->n_multi_hop = (int64_t)h[mmoc::ST_MULTIHOP];
+    out->n_bruteforce = (int64_t)h[mmoc::ST_BRUTE];
+    out->n_tieband = (int64_t)h[mmoc::ST_TIEBAND];
+    out->n_nan = (int64_t)h[mmoc::ST_NAN];
+    out->n_checked = (int64_t)h[mmoc::ST_CHECKED];
+    out->n_fallback = (int64_t)h[mmoc::ST_FALLBACK];
+    double r;
+    std::memcpy(&r, &h[mmoc::ST_MAXRES_BITS], sizeof r);
+    out->max_check_residual = r;
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_reset_stats(mmoc_ctx* c)
+{
+    if (!c) return MMOC_E_ARG;
+    HIPCHK(c, hipMemsetAsync(c->stats_d, 0, sizeof(unsigned long long) * mmoc::ST_COUNT, c->stream), "reset stats");
+    return MMOC_OK;
+}
+
+const char* mmoc_last_error(const mmoc_ctx* c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+void mmoc_destroy(mmoc_ctx* c)
+{
+    if (!c) return;
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"
+
+namespace {
+void free_all(mmoc_ctx* c)
+{
+    mmoc_mlp_free_state(c);
+    (void)hipFree(c->geo_d);
+    (void)hipFree(c->owned_d);
+    (void)hipFree(c->slot_uid_d);
+    (void)hipFree(c->rec_d[0]);
+    (void)hipFree(c->rec_d[1]);
+    (void)hipFree(c->stats_d);
+    c->geo_d = nullptr;
+    c->owned_d = nullptr;
+    c->slot_uid_d = nullptr;
+    c->rec_d[0] = c->rec_d[1] = nullptr;
+    c->stats_d = nullptr;
+}
+}  // namespace

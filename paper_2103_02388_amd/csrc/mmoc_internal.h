@@ -1,0 +1,94 @@
+// mmoc_internal.h -- data layouts shared by the host side of the library and
+// its HIP kernels.  Nothing here is part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mmoc {
+
+// Geometry of one macro element, 256 bytes, read by the kernels from an
+// L2-resident table.  x = v0 + B s (computational domain), s = Binv (x - v0).
+// For the radially blended shell, (pn, pc) is the plane n.x = c through the
+// macro's three unit directions.  nbr[k]: macro across the face opposite
+// local vertex k, -1 on the domain boundary.
+struct alignas(16) MacroGeo {
+    double v0[3];
+    double binv[9];   // row-major
+    double B[9];      // row-major
+    double pn[3];
+    double pc;
+    int32_t nbr[4];
+    float binvf[9];   // float copy of binv for the mixed-precision tracer
+    float pad;
+};
+static_assert(sizeof(MacroGeo) == 256, "MacroGeo must stay 256 bytes");
+
+// Particle table entry: owner macro and lattice coordinates of the DoF a
+// thread traces.  bits 0-11 K, 12-23 J, 24-35 I, 36-63 macro.
+__host__ __device__ inline uint64_t pack_owned(uint32_t M, uint32_t I, uint32_t J, uint32_t K)
+{
+    return ((uint64_t)M << 36) | ((uint64_t)I << 24) | ((uint64_t)J << 12) | (uint64_t)K;
+}
+
+// Statistic counters kept in device memory (uint64 each).
+enum StatSlot {
+    ST_PARTICLES = 0,
+    ST_OUTSIDE,
+    ST_MULTIHOP,
+    ST_BRUTE,
+    ST_TIEBAND,
+    ST_NAN,
+    ST_CHECKED,
+    ST_FALLBACK,
+    ST_MAXRES_BITS,  // max check residual, stored as the bits of a non-negative double
+    ST_COUNT
+};
+
+enum LaneFlag : unsigned {
+    LF_OUTSIDE = 1u,
+    LF_MULTIHOP = 2u,
+    LF_BRUTE = 4u,
+    LF_TIEBAND = 8u,
+    LF_NAN = 16u,
+};
+
+// Arguments of the trace kernels.  Field records are 4-wide per block slot:
+// level 0 holds (u_0 .. u_{dim-1}, ., c) at t_n (c always in component 3),
+// level 1 holds u at t_{n+1}.  T is double (FP64 path) or float (mixed path).
+template <typename T>
+struct TraceArgs {
+    const MacroGeo* geo;
+    const uint64_t* owned;   // [n] particle table (thread order)
+    const T* rec0;           // [n_macros * npm * 4]
+    const T* rec1;           // [n_macros * npm * 4] or null when stationary
+    int64_t n;               // particles traced by this launch (threads)
+    int64_t xstride;         // total particles: stride of X and extent of c_hat
+    int nm;                  // macros
+    int npm;                 // lattice nodes per macro
+    int nlev;                // 1 (stationary) or 2
+    int level_n;             // micro edges per macro edge, 2^level
+    int substeps;
+    int max_hops;
+    double dt;
+    double eps_in;
+    float eps32_macro;
+    float eps32_micro;
+    T* c_hat;                // [n] or null
+    double* X;               // [dim][n] or null
+    const int32_t* ids;      // optional subset of particles to trace (null: all)
+    unsigned long long* stats;
+};
+
+// Launchers (kernels in mmoc_kernels.hip).  Each validates nothing: the host
+// side checks every argument before calling them.
+hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s);
+hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
+hipError_t launch_dof_coords(int dim, int blend, const MacroGeo* geo, const uint64_t* owned,
+                             int64_t n, int level_n, double* out, hipStream_t s);
+hipError_t launch_scatter_vec(int dim, const int32_t* slot_uid, int64_t nslots, const double* u,
+                              int64_t n_unique, void* rec, int fp32, hipStream_t s);
+hipError_t launch_scatter_scalar(const int32_t* slot_uid, int64_t nslots, const double* c,
+                                 void* rec, int fp32, hipStream_t s);
+
+}  // namespace mmoc

@@ -1,0 +1,309 @@
+"""Python binding of the C-ABI in ``include/mmoc.h`` (``libmmoc.so``).
+
+Argument marshalling only: torch tensors are passed as device pointers and
+torch's current HIP stream as the stream handle; every step of the method
+runs in the library's HIP kernels.  The functions keep the C names; each
+raises :class:`MMOCError` with the library's reason when the call fails.
+Importing this module fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from .build import LIB
+
+MMOC_FP64 = 0
+MMOC_FP32_MIXED = 1
+MMOC_BLEND_NONE = 0
+MMOC_BLEND_SHELL_RADIAL = 1
+
+STATUS = {0: "MMOC_OK", -1: "MMOC_E_ARG", -2: "MMOC_E_MESH", -3: "MMOC_E_STATE", -4: "MMOC_E_HIP",
+          -5: "MMOC_E_NOMEM", -6: "MMOC_E_UNSUPPORTED"}
+
+EXPORTED = [
+    "mmoc_default_options", "mmoc_create", "mmoc_set_stream", "mmoc_upload_mesh", "mmoc_num_dofs",
+    "mmoc_dof_coords", "mmoc_set_velocity", "mmoc_set_stationary", "mmoc_swap_velocity_levels",
+    "mmoc_set_scalar", "mmoc_trace_step", "mmoc_get_stats", "mmoc_reset_stats", "mmoc_mlp_nparams",
+    "mmoc_mlp_configure", "mmoc_mlp_record", "mmoc_mlp_train", "mmoc_mlp_get_weights",
+    "mmoc_mlp_set_weights", "mmoc_mlp_infer", "mmoc_trace_step_surrogate", "mmoc_last_error",
+    "mmoc_destroy",
+]
+
+
+class MMOCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class mmoc_options(C.Structure):
+    _fields_ = [("eps_in", C.c_double), ("eps32_macro", C.c_float), ("eps32_micro", C.c_float),
+                ("max_hops", C.c_int), ("reserved", C.c_int * 4)]
+
+
+class mmoc_stats(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("n_outside", C.c_int64), ("n_multi_hop", C.c_int64),
+                ("n_bruteforce", C.c_int64), ("n_tieband", C.c_int64), ("n_nan", C.c_int64),
+                ("n_checked", C.c_int64), ("n_fallback", C.c_int64), ("max_check_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Loads libmmoc.so (raises ImportError if it was never built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        raise ImportError("libmmoc.so is not built (%s); run __graft_entry__.build()" % LIB)
+    L = C.CDLL(LIB)
+    P, I, D, I64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
+    st = C.c_int
+    sig = {
+        "mmoc_default_options": (None, [C.POINTER(mmoc_options)]),
+        "mmoc_create": (st, [C.POINTER(P), I, I, I, C.POINTER(mmoc_options), P]),
+        "mmoc_set_stream": (st, [P, P]),
+        "mmoc_upload_mesh": (st, [P, I, P, I, P, I]),
+        "mmoc_num_dofs": (st, [P, C.POINTER(I64), C.POINTER(I64)]),
+        "mmoc_dof_coords": (st, [P, P]),
+        "mmoc_set_velocity": (st, [P, I, P]),
+        "mmoc_set_stationary": (st, [P, I]),
+        "mmoc_swap_velocity_levels": (st, [P]),
+        "mmoc_set_scalar": (st, [P, P]),
+        "mmoc_trace_step": (st, [P, D, I, P, P]),
+        "mmoc_get_stats": (st, [P, C.POINTER(mmoc_stats)]),
+        "mmoc_reset_stats": (st, [P]),
+        "mmoc_mlp_nparams": (I64, []),
+        "mmoc_mlp_configure": (st, [P, P, P, D]),
+        "mmoc_mlp_record": (st, [P, D, D, P, I64]),
+        "mmoc_mlp_train": (st, [P, I64, I, I, C.c_float, C.c_ulonglong, C.POINTER(D)]),
+        "mmoc_mlp_get_weights": (st, [P, P, I64]),
+        "mmoc_mlp_set_weights": (st, [P, P, I64]),
+        "mmoc_mlp_infer": (st, [P, D, D, P]),
+        "mmoc_trace_step_surrogate": (st, [P, D, D, I, C.c_float, D, I64, P, P]),
+        "mmoc_last_error": (C.c_char_p, [P]),
+        "mmoc_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _check(ctx, status):
+    if status != 0:
+        msg = lib().mmoc_last_error(ctx).decode() if ctx else ""
+        raise MMOCError(status, msg)
+
+
+# ----------------------------------------------------------------- C names
+
+def mmoc_default_options():
+    o = mmoc_options()
+    lib().mmoc_default_options(C.byref(o))
+    return o
+
+
+def mmoc_create(dim, level, prec=MMOC_FP64, opt: Optional[mmoc_options] = None, stream=None):
+    h = C.c_void_p()
+    s = lib().mmoc_create(C.byref(h), int(dim), int(level), int(prec),
+                          C.byref(opt) if opt is not None else None, _stream(stream))
+    if s != 0:
+        raise MMOCError(s, "mmoc_create failed")
+    return h
+
+
+def mmoc_set_stream(ctx, stream=None):
+    _check(ctx, lib().mmoc_set_stream(ctx, _stream(stream)))
+
+
+def mmoc_upload_mesh(ctx, vertices: np.ndarray, macros: np.ndarray, blend=MMOC_BLEND_NONE):
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    m = np.ascontiguousarray(macros, dtype=np.int32)
+    _check(ctx, lib().mmoc_upload_mesh(ctx, v.shape[0], v.ctypes.data_as(C.c_void_p), m.shape[0],
+                                       m.ctypes.data_as(C.c_void_p), int(blend)))
+
+
+def mmoc_num_dofs(ctx):
+    n, b = C.c_int64(), C.c_int64()
+    _check(ctx, lib().mmoc_num_dofs(ctx, C.byref(n), C.byref(b)))
+    return n.value, b.value
+
+
+def mmoc_dof_coords(ctx, out: torch.Tensor):
+    _check(ctx, lib().mmoc_dof_coords(ctx, _ptr(out)))
+
+
+def mmoc_set_velocity(ctx, level, u: torch.Tensor):
+    _check(ctx, lib().mmoc_set_velocity(ctx, int(level), _ptr(u)))
+
+
+def mmoc_set_stationary(ctx, on):
+    _check(ctx, lib().mmoc_set_stationary(ctx, int(bool(on))))
+
+
+def mmoc_swap_velocity_levels(ctx):
+    _check(ctx, lib().mmoc_swap_velocity_levels(ctx))
+
+
+def mmoc_set_scalar(ctx, c: torch.Tensor):
+    _check(ctx, lib().mmoc_set_scalar(ctx, _ptr(c)))
+
+
+def mmoc_trace_step(ctx, dt, substeps, c_hat: torch.Tensor, X: Optional[torch.Tensor]):
+    _check(ctx, lib().mmoc_trace_step(ctx, float(dt), int(substeps), _ptr(c_hat), _ptr(X)))
+
+
+def mmoc_get_stats(ctx):
+    s = mmoc_stats()
+    _check(ctx, lib().mmoc_get_stats(ctx, C.byref(s)))
+    return s.as_dict()
+
+
+def mmoc_reset_stats(ctx):
+    _check(ctx, lib().mmoc_reset_stats(ctx))
+
+
+def mmoc_mlp_nparams():
+    return int(lib().mmoc_mlp_nparams())
+
+
+def mmoc_mlp_configure(ctx, lo, hi, U):
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    _check(ctx, lib().mmoc_mlp_configure(ctx, lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p),
+                                         float(U)))
+
+
+def mmoc_mlp_record(ctx, t_np1, dt, X: torch.Tensor, capacity):
+    _check(ctx, lib().mmoc_mlp_record(ctx, float(t_np1), float(dt), _ptr(X), int(capacity)))
+
+
+def mmoc_mlp_train(ctx, n_samples, epochs, batch, lr, seed):
+    loss = C.c_double()
+    _check(ctx, lib().mmoc_mlp_train(ctx, int(n_samples), int(epochs), int(batch), float(lr), int(seed),
+                                     C.byref(loss)))
+    return loss.value
+
+
+def mmoc_mlp_get_weights(ctx):
+    n = mmoc_mlp_nparams()
+    w = np.empty(n, dtype=np.float32)
+    _check(ctx, lib().mmoc_mlp_get_weights(ctx, w.ctypes.data_as(C.c_void_p), n))
+    return w
+
+
+def mmoc_mlp_set_weights(ctx, w):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _check(ctx, lib().mmoc_mlp_set_weights(ctx, w.ctypes.data_as(C.c_void_p), w.shape[0]))
+
+
+def mmoc_mlp_infer(ctx, t_np1, dt, X: torch.Tensor):
+    _check(ctx, lib().mmoc_mlp_infer(ctx, float(t_np1), float(dt), _ptr(X)))
+
+
+def mmoc_trace_step_surrogate(ctx, t_np1, dt, substeps, check_fraction, tol, step, c_hat, X):
+    _check(ctx, lib().mmoc_trace_step_surrogate(ctx, float(t_np1), float(dt), int(substeps),
+                                                float(check_fraction), float(tol), int(step), _ptr(c_hat),
+                                                _ptr(X)))
+
+
+def mmoc_last_error(ctx):
+    return lib().mmoc_last_error(ctx).decode()
+
+
+def mmoc_destroy(ctx):
+    lib().mmoc_destroy(ctx)
+
+
+# ------------------------------------------------------------ convenience
+
+class Tracer:
+    """Owns one library context on the current device (torch's current stream)."""
+
+    def __init__(self, dim, level, vertices, macros, blend=0, precision=MMOC_FP64, options=None, stream=None):
+        self.dim, self.level, self.precision = int(dim), int(level), int(precision)
+        self.ctx = mmoc_create(dim, level, precision, options, stream)
+        try:
+            mmoc_upload_mesh(self.ctx, vertices, macros, blend)
+        except Exception:
+            mmoc_destroy(self.ctx)
+            self.ctx = None
+            raise
+        self.N, self.n_block = mmoc_num_dofs(self.ctx)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_workload(cls, wl, precision=MMOC_FP64, level=None, options=None):
+        return cls(wl.dim, wl.level if level is None else level, wl.vertices, wl.macros, wl.blend, precision,
+                   options)
+
+    def close(self):
+        if self.ctx is not None:
+            mmoc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def scalar_dtype(self):
+        return torch.float64 if self.precision == MMOC_FP64 else torch.float32
+
+    def dof_coords(self):
+        x = torch.empty((self.dim, self.N), dtype=torch.float64, device=self.device)
+        mmoc_dof_coords(self.ctx, x)
+        return x
+
+    def set_velocity(self, level, u):
+        mmoc_set_velocity(self.ctx, level, u)
+
+    def set_stationary(self, on=True):
+        mmoc_set_stationary(self.ctx, on)
+
+    def set_scalar(self, c):
+        mmoc_set_scalar(self.ctx, c)
+
+    def swap_levels(self):
+        mmoc_swap_velocity_levels(self.ctx)
+
+    def trace_step(self, dt, substeps, c_hat=None, X=None, want_X=True):
+        if c_hat is None:
+            c_hat = torch.empty(self.N, dtype=self.scalar_dtype, device=self.device)
+        if X is None and want_X:
+            X = torch.empty((self.dim, self.N), dtype=torch.float64, device=self.device)
+        mmoc_trace_step(self.ctx, dt, substeps, c_hat, X)
+        return c_hat, X
+
+    def stats(self):
+        return mmoc_get_stats(self.ctx)
+
+    def reset_stats(self):
+        mmoc_reset_stats(self.ctx)

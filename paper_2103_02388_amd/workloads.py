@@ -264,34 +264,38 @@ def exp_profile_z(x: torch.Tensor) -> torch.Tensor:
 # --- spherical-shell modes --------------------------------------------------
 
 
-def _real_sph_harm(l: int, m: int, ct: torch.Tensor, phi: torch.Tensor) -> torch.Tensor:
-    """Real orthonormal spherical harmonic Y_lm(theta, phi), ct = cos(theta)."""
+def _real_sph_harm(l: int, m: int, x: torch.Tensor) -> torch.Tensor:
+    """Real orthonormal spherical harmonic Y_lm at the direction of x (rows).
+
+    Written in Cartesian form so that it is smooth everywhere off the origin
+    (no angles): with u = x/|x|, P_l^|m|(u_z) = (1 - u_z^2)^(|m|/2) Q(u_z) for a
+    polynomial Q, and (1 - u_z^2)^(|m|/2) (cos |m| phi, sin |m| phi) are the real
+    and imaginary parts of (u_x + i u_y)^|m|.  No Condon-Shortley phase.
+    """
     am = abs(m)
-    st = torch.sqrt(torch.clamp(1.0 - ct * ct, min=0.0))
-    # associated Legendre P_am^am, then upward recurrence in l (no Condon-Shortley phase)
-    pmm = torch.ones_like(ct)
-    fact = 1.0
-    for _ in range(am):
-        pmm = pmm * fact * st
-        fact += 2.0
+    r = torch.linalg.norm(x, dim=1)
+    ux, uy, uz = x[:, 0] / r, x[:, 1] / r, x[:, 2] / r
+    # Q_am^am = (2am - 1)!!, Q_{am+1}^am = (2am + 1) u_z Q_am^am, then upward in l
+    dfact = 1.0
+    for k in range(1, 2 * am, 2):
+        dfact *= k
+    q0 = torch.full_like(uz, dfact)
     if l == am:
-        plm = pmm
+        q = q0
     else:
-        pmmp1 = ct * (2 * am + 1) * pmm
-        if l == am + 1:
-            plm = pmmp1
-        else:
-            p0, p1 = pmm, pmmp1
-            for ll in range(am + 2, l + 1):
-                p2 = ((2 * ll - 1) * ct * p1 - (ll + am - 1) * p0) / (ll - am)
-                p0, p1 = p1, p2
-            plm = p1
+        q1 = uz * (2 * am + 1) * q0
+        for ll in range(am + 2, l + 1):
+            q0, q1 = q1, ((2 * ll - 1) * uz * q1 - (ll + am - 1) * q0) / (ll - am)
+        q = q1
+    re, im = torch.ones_like(ux), torch.zeros_like(ux)
+    for _ in range(am):
+        re, im = re * ux - im * uy, re * uy + im * ux
     norm = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
     if m > 0:
-        return math.sqrt(2.0) * norm * plm * torch.cos(am * phi)
+        return math.sqrt(2.0) * norm * q * re
     if m < 0:
-        return math.sqrt(2.0) * norm * plm * torch.sin(am * phi)
-    return norm * plm
+        return math.sqrt(2.0) * norm * q * im
+    return norm * q
 
 
 class ShellModes:
@@ -319,15 +323,25 @@ class ShellModes:
 
     def _pot(self, x, kind):
         r = torch.linalg.norm(x, dim=1)
-        ct = x[:, 2] / r
-        phi = torch.atan2(x[:, 1], x[:, 0])
         rho = (r - self.r_min) / (self.r_max - self.r_min)
         radial = torch.sin(math.pi * rho)
         out = torch.zeros_like(r)
         for (k, l, m, a) in self.modes:
             if k == kind:
-                out = out + a * radial * _real_sph_harm(l, m, ct, phi)
+                out = out + a * radial * _real_sph_harm(l, m, x)
         return out
+
+    def normalise(self, n_points: int = 1 << 18, seed: int = 30):
+        """Scales the field so that its largest speed over a seeded uniform
+        sample of the shell is 1."""
+        rng = np.random.default_rng(seed)
+        d = rng.normal(size=(n_points, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        r = (self.r_min ** 3 + rng.uniform(size=(n_points, 1)) * (self.r_max ** 3 - self.r_min ** 3)) ** (1 / 3)
+        self.scale = 1.0
+        u = self.velocity(torch.from_numpy(d * r))
+        self.scale = 1.0 / float(torch.linalg.norm(u, dim=1).max())
+        return self
 
     def velocity(self, x: torch.Tensor, t: float = 0.0, batch: int = 1 << 21) -> torch.Tensor:
         outs = []
@@ -427,7 +441,7 @@ def shell3d(level: int = 5, subdiv: int = 4, layers: int = 4) -> Workload:
     normalises the field so that the largest nodal speed is 1 (``scale``).
     """
     v, m = shell(subdiv, layers)
-    sm = ShellModes()
+    sm = ShellModes().normalise()
     h_min = (1.0 - 0.55) / layers / (2 ** level)
     return Workload("shell3d", 3, level, v, m, 1, 5.0 * h_min, 4, 1, True,
                     sm.velocity, shell_step_scalar,

@@ -1,0 +1,128 @@
+"""The C-ABI: every symbol declared in include/mmoc.h is exported (CPU), and
+argument, state and mesh errors come back as the documented codes before any
+device work is enqueued (GPU)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2103_02388_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "mmoc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mmoc_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2103_02388_amd import mmoc
+    L = mmoc.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(mmoc.EXPORTED)
+
+
+def test_default_options_and_param_count():
+    from paper_2103_02388_amd import mmoc
+    o = mmoc.mmoc_default_options()
+    assert o.eps_in == 1e-12 and o.max_hops == 64
+    assert mmoc.mmoc_mlp_nparams() == 4 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * 3 + 3
+
+
+@pytest.mark.gpu
+def test_argument_and_state_errors():
+    import torch
+    from paper_2103_02388_amd import mmoc
+    wl = W.swirl3d(level=4)
+    tr = mmoc.Tracer.from_workload(wl)
+    N = tr.N
+    assert 8 * N > 4 * 65536
+    dev = tr.device
+    c = torch.zeros(N, dtype=torch.float64, device=dev)
+    X = torch.zeros((3, N), dtype=torch.float64, device=dev)
+    # trace before fields are set
+    with pytest.raises(mmoc.MMOCError) as e:
+        tr.trace_step(0.1, 4, c, X)
+    assert e.value.status == -3
+    u = torch.zeros((3, N), dtype=torch.float64, device=dev)
+    tr.set_velocity(0, u)
+    tr.set_stationary(True)
+    with pytest.raises(mmoc.MMOCError) as e:
+        tr.trace_step(0.1, 4, c, X)  # scalar missing
+    assert e.value.status == -3
+    tr.set_scalar(c)
+    tr.trace_step(0.1, 4, c, X)
+    for bad in ((0.0, 4), (-1.0, 4), (float("nan"), 4), (0.1, 0)):
+        with pytest.raises(mmoc.MMOCError) as e:
+            tr.trace_step(bad[0], bad[1], c, X)
+        assert e.value.status == -1
+    # host memory, too-small buffers, misaligned pointers
+    host = torch.zeros(N, dtype=torch.float64)
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.mmoc_trace_step(tr.ctx, 0.1, 4, host, X)
+    assert e.value.status == -1
+    # a buffer that ends before the data would: the library sees the end of a
+    # device allocation (not the sub-allocations of torch's caching allocator),
+    # so the test makes its own allocation of exactly 8 N bytes and passes a
+    # pointer 64 KiB into it
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    raw_p = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(raw_p), ctypes.c_size_t(8 * N)) == 0
+    try:
+        late = ctypes.c_void_p(raw_p.value + 65536)
+        st = mmoc.lib().mmoc_trace_step(tr.ctx, 0.1, 4, late, ctypes.c_void_p(X.data_ptr()))
+        assert st == -1, st
+        st = mmoc.lib().mmoc_set_scalar(tr.ctx, late)
+        assert st == -1, st
+        st = mmoc.lib().mmoc_set_scalar(tr.ctx, raw_p)
+        assert st == 0, st
+    finally:
+        hip.hipDeviceSynchronize()
+        hip.hipFree(raw_p)
+    raw = torch.zeros(8 * N + 16, dtype=torch.uint8, device=dev)
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.mmoc_set_scalar(tr.ctx, raw[1:])
+    assert e.value.status == -1
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.mmoc_set_velocity(tr.ctx, 2, u)
+    assert e.value.status == -1
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.mmoc_swap_velocity_levels(tr.ctx)  # level 1 never set
+    assert e.value.status == -3
+    tr.close()
+
+
+@pytest.mark.gpu
+def test_mesh_errors():
+    from paper_2103_02388_amd import mmoc
+    v, m = W.cube6()
+    # degenerate macro (repeated coordinates)
+    v2 = v.copy()
+    v2[7] = v2[3]
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.Tracer(3, 1, v2, m)
+    assert e.value.status == -2
+    # non-conforming vertex order on a shared face
+    m2 = m.copy()
+    m2[0] = m2[0][[3, 1, 2, 0]]
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.Tracer(3, 1, v, m2)
+    assert e.value.status == -2
+    # vertex id out of range
+    m3 = m.copy()
+    m3[1, 2] = 99
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.Tracer(3, 1, v, m3)
+    assert e.value.status == -2
+    # shell blending in 2D is not built
+    vs, ms = W.square2()
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.Tracer(2, 1, vs, ms, blend=1)
+    assert e.value.status == -6

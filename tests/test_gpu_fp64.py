@@ -1,0 +1,185 @@
+"""FP64 tracer on the GPU vs the CPU oracle, element by element.
+
+Tolerance: 1e-12 relative in departure points and interpolated values (the
+relative measures are defined in gpu_helpers).  Sizes: the 2D rotation
+(16641 particles) and 3D swirl (274625) workloads at full size, plus small
+meshes for edge cases (ragged tails: neither count is a multiple of 256).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2103_02388_amd import mmoc
+from paper_2103_02388_amd import workloads as W
+
+from gpu_helpers import Pair, field_cpu, field_gpu, rel_c, rel_x
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def check(pair, ch, X, chr_, Xr):
+    ex, ec = rel_x(X, Xr), rel_c(ch, chr_)
+    assert ex <= TOL, ex
+    assert ec <= TOL, ec
+    return ex, ec
+
+
+def test_rotation2d_full_size():
+    wl = W.rotation2d()
+    p = Pair(wl)
+    assert p.tr.N == 16641
+    assert p.coord_err < 1e-15
+    p.set_fields(0.0, wl.dt, True)
+    p.tr.reset_stats()
+    ch, X = p.gpu_step(wl.dt, wl.substeps)
+    chr_, Xr, st = p.oracle_step(wl.dt, wl.substeps)
+    check(p, ch, X, chr_, Xr)
+    gs = p.tr.stats()
+    assert gs["n_particles"] == p.tr.N
+    assert gs["n_outside"] == st[0] > 0  # rotation leaves the square at the corners
+    assert gs["n_nan"] == 0
+
+
+@pytest.mark.parametrize("step,S", [(7, 4), (0, 1), (13, 2)])
+def test_swirl3d_full_size(step, S):
+    wl = W.swirl3d()
+    p = Pair(wl)
+    assert p.tr.N == 274625
+    assert p.coord_err < 1e-15
+    t_n = step * wl.dt
+    p.set_fields(t_n, wl.dt, False)
+    p.tr.reset_stats()
+    ch, X = p.gpu_step(wl.dt, S)
+    chr_, Xr, st = p.oracle_step(wl.dt, S, threads=8)
+    check(p, ch, X, chr_, Xr)
+    gs = p.tr.stats()
+    assert gs["n_particles"] == p.tr.N and gs["n_nan"] == 0
+    assert abs(gs["n_multi_hop"] - st[1]) <= 2 and abs(gs["n_outside"] - st[0]) <= 2
+
+
+def test_large_displacement_many_hops_and_exits():
+    """dt = T with 2 sub-steps: stage points cross several macros and leave the cube."""
+    wl = W.swirl3d()
+    p = Pair(wl, level=2)
+    p.set_fields(0.1, 1.5, False)
+    p.tr.reset_stats()
+    ch, X = p.gpu_step(1.5, 2)
+    chr_, Xr, st = p.oracle_step(1.5, 2)
+    check(p, ch, X, chr_, Xr)
+    gs = p.tr.stats()
+    assert gs["n_multi_hop"] > 0 and st[1] > 0
+
+
+def test_brute_force_location_gives_the_same_step():
+    """max_hops = 0 sends every macro change to brute force; the result must not change."""
+    wl = W.swirl3d()
+    opt = mmoc.mmoc_default_options()
+    opt.max_hops = 0
+    p = Pair(wl, level=3, options=opt)
+    p.set_fields(0.3, wl.dt, False)
+    p.tr.reset_stats()
+    ch, X = p.gpu_step(wl.dt, 4)
+    chr_, Xr, st = p.oracle_step(wl.dt, 4, max_hops=0)
+    check(p, ch, X, chr_, Xr)
+    chr2, Xr2, _ = p.oracle_step(wl.dt, 4)
+    assert rel_x(Xr, Xr2) <= TOL and rel_c(chr_, chr2) <= TOL
+    assert p.tr.stats()["n_bruteforce"] > 0
+
+
+def test_small_meshes_every_level():
+    for level in (0, 1, 2, 3):
+        for wl in (W.rotation2d(), W.swirl3d()):
+            p = Pair(wl, level=level)
+            assert p.coord_err < 1e-15
+            p.set_fields(0.2, wl.dt * 3, wl.stationary)
+            ch, X = p.gpu_step(wl.dt * 3, 3)
+            chr_, Xr, _ = p.oracle_step(wl.dt * 3, 3)
+            check(p, ch, X, chr_, Xr)
+
+
+def test_stationary_equals_two_identical_levels():
+    wl = W.swirl3d()
+    p = Pair(wl, level=3)
+    p.set_fields(0.4, wl.dt, True)
+    ch1, X1 = p.gpu_step(wl.dt, 4)
+    p.tr.set_stationary(False)
+    p.tr.set_velocity(1, p.u0g)
+    ch2, X2 = p.gpu_step(wl.dt, 4)
+    assert rel_x(X1, X2) <= 1e-15 and rel_c(ch1, ch2) <= 1e-15
+
+
+def test_multi_step_chain_with_level_swap():
+    """Five consecutive steps (levels swapped, chat fed back as the next scalar)
+    against the oracle's own chain; the two chains drift only by rounding."""
+    wl = W.swirl3d()
+    p = Pair(wl, level=3)
+    dt, S = wl.dt, 4
+    p.set_fields(0.0, dt, False)
+    cg, cc = p.cg, p.cc
+    u0c = p.u0c
+    for n in range(5):
+        t_n = n * dt
+        if n > 0:
+            p.tr.swap_levels()
+            u1g = field_gpu(wl.velocity, p.xg, t_n + dt)
+            p.tr.set_velocity(1, u1g)
+            p.tr.set_scalar(cg)
+        u1c = field_cpu(wl.velocity, p.xc, t_n + dt)
+        chg, Xg = p.tr.trace_step(dt, S)
+        torch.cuda.synchronize()
+        chc, Xc, _ = p.om.trace(u0c, u1c, cc, dt, S)
+        assert rel_x(Xg.cpu().numpy(), Xc) <= TOL
+        assert rel_c(chg.cpu().numpy(), chc) <= 1e-11
+        cg, cc, u0c = chg.contiguous(), chc, u1c
+
+
+def test_shell_blended_fp64():
+    wl = W.shell3d(level=1)
+    p = Pair(wl, level=1)
+    assert p.coord_err < 1e-14
+    p.set_fields(0.0, wl.dt, True)
+    p.tr.reset_stats()
+    ch, X = p.gpu_step(wl.dt, 4)
+    chr_, Xr, st = p.oracle_step(wl.dt, 4)
+    check(p, ch, X, chr_, Xr)
+    assert p.tr.stats()["n_nan"] == 0
+
+
+def test_nan_velocity_is_counted_and_contained():
+    wl = W.swirl3d()
+    p = Pair(wl, level=2)
+    p.set_fields(0.3, wl.dt, False)
+    u = p.u0g.clone()
+    u[0, p.tr.N // 2] = float("nan")
+    p.tr.set_velocity(0, u)
+    p.tr.reset_stats()
+    ch, X = p.gpu_step(wl.dt, 4)
+    st = p.tr.stats()
+    nbad = int(np.isnan(X).any(axis=0).sum())
+    assert 0 < nbad < p.tr.N // 4
+    assert st["n_nan"] == nbad
+
+
+def test_two_runs_are_bitwise_identical():
+    wl = W.swirl3d()
+    p = Pair(wl, level=4)
+    p.set_fields(0.5, wl.dt, False)
+    a = p.gpu_step(wl.dt, 4)
+    b = p.gpu_step(wl.dt, 4)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_plume3d_full_size_sampled():
+    """1.7e7 particles on the GPU; the oracle traces a seeded sample of 3000."""
+    wl = W.plume3d()
+    p = Pair(wl)
+    assert p.tr.N == 257 ** 3
+    assert p.coord_err < 1e-15
+    step = 60
+    p.set_fields(step * wl.dt, wl.dt, False)
+    ch, X = p.gpu_step(wl.dt, 4)
+    ids = np.sort(np.random.default_rng(12).choice(p.tr.N, 3000, replace=False))
+    chr_, Xr, _ = p.oracle_step(wl.dt, 4, ids=ids, threads=8)
+    ex, ec = rel_x(X[:, ids], Xr), rel_c(ch[ids], chr_)
+    assert ex <= TOL and ec <= TOL
