@@ -76,7 +76,12 @@ typedef struct {
     double eps_in;     /* macro acceptance: min barycentric >= -eps_in (default 1e-12) */
     float eps32_macro; /* FP32 path: macro decisions with |min lambda| < eps redone in FP64 (4e-6) */
     float eps32_micro; /* FP32 path: micro decisions with a sorted-coordinate gap < eps*n
-                          redone in FP64 (2^-17) */
+                          redone in FP64 (default 0: off.  The P2 field is continuous
+                          across micro faces, so a micro tie changes the value only by
+                          rounding; particles of a slow flow sit within float32
+                          rounding of a lattice node at every stage and would all be
+                          re-located.  Float32 rounding of the lattice coordinates
+                          is about n * 1e-6; 2^-18 is a sound non-zero band) */
     int max_hops;      /* walk hops before brute-force location (default 64) */
     int reserved[4];
 } mmoc_options;
@@ -134,12 +139,14 @@ mmoc_status mmoc_dof_coords(mmoc_ctx* ctx, double* xyz_dev);
  * stream has passed this call. */
 mmoc_status mmoc_set_velocity(mmoc_ctx* ctx, int level, const double* u_dev);
 
-/* on != 0: the velocity is stationary; only level 0 is used (level 1 need not
- * be set) and each stage evaluates one field. */
+/* on != 0: the velocity is stationary; only level 0 is used (setting level 1
+ * is an MMOC_E_STATE error) and each stage evaluates one field.  Switching
+ * back to two levels requires level 1 to be set again. */
 mmoc_status mmoc_set_stationary(mmoc_ctx* ctx, int on);
 
 /* Makes level 1 the new level 0 (u^{n+1} becomes u^n for the next step, no
- * copy).  Level 1 and the scalar must be set again before the next trace. */
+ * copy).  Level 1 must be set again before the next trace; the scalar keeps
+ * its value until mmoc_set_scalar is called. */
 mmoc_status mmoc_swap_velocity_levels(mmoc_ctx* ctx);
 
 /* Sets the scalar c_h^n from a unique-layout [n_unique] float64 device array

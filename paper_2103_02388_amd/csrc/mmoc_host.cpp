@@ -41,9 +41,12 @@ struct mmoc_ctx {
     int nm = 0;
     int64_t npm = 0, nslots = 0, N = 0;
     MacroGeo* geo_d = nullptr;
-    uint64_t* owned_d = nullptr;
+    uint64_t* owned_d = nullptr;     // unique order
     int32_t* slot_uid_d = nullptr;
-    void* rec_d[2] = {nullptr, nullptr};
+    void* va_d[2] = {nullptr, nullptr};  // per level: (u_x,u_y) pairs, or (u_x,u_y,u_z) triples (3D float32)
+    void* vb_d[2] = {nullptr, nullptr};  // per level: u_z (3D float64)
+    void* cs_d = nullptr;                // scalar
+    int swap = 0;                        // array set holding t_n
     bool vel_set[2] = {false, false};
     bool scalar_set = false;
     bool stationary = false;
@@ -172,7 +175,7 @@ void mmoc_default_options(mmoc_options* o)
     std::memset(o, 0, sizeof *o);
     o->eps_in = 1e-12;
     o->eps32_macro = 4e-6f;
-    o->eps32_micro = 1.0f / 131072.0f;
+    o->eps32_micro = 0.0f;  // micro ties are value-neutral (P2 is continuous across micro faces)
     o->max_hops = 64;
 }
 
@@ -406,12 +409,26 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
     if ((st = dev_alloc(c, &c->geo_d, nm, "geometry")) != MMOC_OK) return st;
     if ((st = dev_alloc(c, &c->owned_d, (size_t)N, "particle table")) != MMOC_OK) return st;
     if ((st = dev_alloc(c, &c->slot_uid_d, (size_t)c->nslots, "slot map")) != MMOC_OK) return st;
-    const size_t elem = c->prec == MMOC_FP64 ? sizeof(double) : sizeof(float);
+    const bool f32 = c->prec == MMOC_FP32_MIXED;
+    const size_t elem = f32 ? sizeof(float) : sizeof(double);
+    const int na = (d == 3 && f32) ? 3 : 2;  // components in the va records
+    if ((uint64_t)c->nslots * na * elem >= (1ull << 32))
+        return fail(c, MMOC_E_ARG, "mesh too large: field arrays must stay below 4 GiB for 32-bit slot offsets");
+    auto alloc_clear = [&](void** p, size_t bytes, const char* what) -> mmoc_status {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return hip_fail(c, e, what);
+        }
+        HIPCHK(c, hipMemsetAsync(*p, 0, bytes, c->stream), what);
+        return MMOC_OK;
+    };
     for (int l = 0; l < 2; ++l) {
-        hipError_t e = hipMalloc(&c->rec_d[l], (size_t)c->nslots * 4 * elem);
-        if (e != hipSuccess) return hip_fail(c, e, "field records");
-        HIPCHK(c, hipMemsetAsync(c->rec_d[l], 0, (size_t)c->nslots * 4 * elem, c->stream), "clear records");
+        if ((st = alloc_clear(&c->va_d[l], (size_t)c->nslots * na * elem, "velocity arrays")) != MMOC_OK) return st;
+        if (d == 3 && !f32 && (st = alloc_clear(&c->vb_d[l], (size_t)c->nslots * elem, "velocity arrays")) != MMOC_OK)
+            return st;
     }
+    if ((st = alloc_clear(&c->cs_d, (size_t)c->nslots * elem, "scalar array")) != MMOC_OK) return st;
     HIPCHK(c, hipMemcpyAsync(c->geo_d, geo.data(), sizeof(MacroGeo) * nm, hipMemcpyHostToDevice, c->stream), "upload geometry");
     HIPCHK(c, hipMemcpyAsync(c->owned_d, owned.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, c->stream), "upload particles");
     HIPCHK(c, hipMemcpyAsync(c->slot_uid_d, slot_uid.data(), sizeof(int32_t) * c->nslots, hipMemcpyHostToDevice, c->stream),
@@ -445,10 +462,28 @@ mmoc_status mmoc_set_velocity(mmoc_ctx* c, int level, const double* u)
     if (!c) return MMOC_E_ARG;
     if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
     if (level != 0 && level != 1) return fail(c, MMOC_E_ARG, "level must be 0 or 1");
+    if (c->stationary && level == 1) return fail(c, MMOC_E_STATE, "stationary velocity: only level 0 is used");
     mmoc_status st = check_dev(c, u, sizeof(double) * c->dim * c->N, 8, "u_dev");
     if (st != MMOC_OK) return st;
-    HIPCHK(c, mmoc::launch_scatter_vec(c->dim, c->slot_uid_d, c->nslots, u, c->N, c->rec_d[level],
-                                       c->prec == MMOC_FP32_MIXED, c->stream),
+    const int L = level ^ c->swap;
+    mmoc::ScatterDst d{};
+    if (c->dim == 3 && c->prec == MMOC_FP64) {
+        d.dst[0] = d.dst[1] = c->va_d[L];
+        d.dst[2] = c->vb_d[L];
+        d.stride[0] = d.stride[1] = 2;
+        d.stride[2] = 1;
+        d.off[0] = 0;
+        d.off[1] = 1;
+        d.off[2] = 0;
+    } else {
+        const int na = c->dim == 3 ? 3 : 2;
+        for (int i = 0; i < c->dim; ++i) {
+            d.dst[i] = c->va_d[L];
+            d.stride[i] = na;
+            d.off[i] = i;
+        }
+    }
+    HIPCHK(c, mmoc::launch_scatter(c->dim, c->slot_uid_d, c->nslots, u, c->N, d, c->prec == MMOC_FP32_MIXED, c->stream),
            "set_velocity");
     c->vel_set[level] = true;
     return MMOC_OK;
@@ -458,6 +493,7 @@ mmoc_status mmoc_set_stationary(mmoc_ctx* c, int on)
 {
     if (!c) return MMOC_E_ARG;
     c->stationary = on != 0;
+    if (c->stationary) c->vel_set[1] = false;
     return MMOC_OK;
 }
 
@@ -465,11 +501,11 @@ mmoc_status mmoc_swap_velocity_levels(mmoc_ctx* c)
 {
     if (!c) return MMOC_E_ARG;
     if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (c->stationary) return fail(c, MMOC_E_STATE, "stationary velocity has one level");
     if (!c->vel_set[1]) return fail(c, MMOC_E_STATE, "velocity level 1 is not set");
-    std::swap(c->rec_d[0], c->rec_d[1]);
+    c->swap ^= 1;
     c->vel_set[0] = true;
     c->vel_set[1] = false;
-    c->scalar_set = false;  // the scalar lives in the level-0 records
     return MMOC_OK;
 }
 
@@ -479,7 +515,11 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
     if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
     mmoc_status st = check_dev(c, cs, sizeof(double) * c->N, 8, "c_dev");
     if (st != MMOC_OK) return st;
-    HIPCHK(c, mmoc::launch_scatter_scalar(c->slot_uid_d, c->nslots, cs, c->rec_d[0], c->prec == MMOC_FP32_MIXED, c->stream),
+    mmoc::ScatterDst d{};
+    d.dst[0] = c->cs_d;
+    d.stride[0] = 1;
+    d.off[0] = 0;
+    HIPCHK(c, mmoc::launch_scatter(1, c->slot_uid_d, c->nslots, cs, c->N, d, c->prec == MMOC_FP32_MIXED, c->stream),
            "set_scalar");
     c->scalar_set = true;
     return MMOC_OK;
@@ -487,18 +527,15 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
 
 }  // extern "C"
 
-// Shared by the plain and the surrogate step: validates and launches the RK4
-// tracer on `n` particles (ids == null: all, in canonical order).
-mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* ids,
+// Shared by the plain and the surrogate step: launches the RK4 tracer on n
+// particles whose unique ids are order[0..n) (all particles: the lane order).
+mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* order,
                               int64_t n)
 {
-    const bool f32 = c->prec == MMOC_FP32_MIXED;
-    if (f32) {
-        mmoc::TraceArgs<float> a{};
+    auto fill = [&](auto& a) {
         a.geo = c->geo_d;
         a.owned = c->owned_d;
-        a.rec0 = (const float*)c->rec_d[0];
-        a.rec1 = c->stationary ? nullptr : (const float*)c->rec_d[1];
+        a.order = order;
         a.n = n;
         a.xstride = c->N;
         a.nm = c->nm;
@@ -511,31 +548,28 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.eps_in = c->opt.eps_in;
         a.eps32_macro = c->opt.eps32_macro;
         a.eps32_micro = c->opt.eps32_micro;
-        a.c_hat = (float*)c_hat;
         a.X = X;
-        a.ids = ids;
         a.stats = c->stats_d;
+    };
+    if (c->prec == MMOC_FP32_MIXED) {
+        mmoc::TraceArgs<float> a{};
+        fill(a);
+        for (int l = 0; l < 2; ++l) {
+            a.va[l] = (const float*)c->va_d[l ^ c->swap];
+            a.vb[l] = (const float*)c->vb_d[l ^ c->swap];
+        }
+        a.cs = (const float*)c->cs_d;
+        a.c_hat = (float*)c_hat;
         HIPCHK(c, mmoc::launch_trace_fp32(c->dim, c->blend, a, c->stream), "trace (fp32 mixed)");
     } else {
         mmoc::TraceArgs<double> a{};
-        a.geo = c->geo_d;
-        a.owned = c->owned_d;
-        a.rec0 = (const double*)c->rec_d[0];
-        a.rec1 = c->stationary ? nullptr : (const double*)c->rec_d[1];
-        a.n = n;
-        a.xstride = c->N;
-        a.nm = c->nm;
-        a.npm = (int)c->npm;
-        a.nlev = c->stationary ? 1 : 2;
-        a.level_n = c->n;
-        a.substeps = substeps;
-        a.max_hops = c->opt.max_hops;
-        a.dt = dt;
-        a.eps_in = c->opt.eps_in;
+        fill(a);
+        for (int l = 0; l < 2; ++l) {
+            a.va[l] = (const double*)c->va_d[l ^ c->swap];
+            a.vb[l] = (const double*)c->vb_d[l ^ c->swap];
+        }
+        a.cs = (const double*)c->cs_d;
         a.c_hat = (double*)c_hat;
-        a.X = X;
-        a.ids = ids;
-        a.stats = c->stats_d;
         HIPCHK(c, mmoc::launch_trace_fp64(c->dim, c->blend, a, c->stream), "trace (fp64)");
     }
     return MMOC_OK;
@@ -602,7 +636,7 @@ const char* mmoc_last_error(const mmoc_ctx* c)
 void mmoc_destroy(mmoc_ctx* c)
 {
     if (!c) return;
-    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     free_all(c);
     delete c;
 }
@@ -616,13 +650,17 @@ void free_all(mmoc_ctx* c)
     (void)hipFree(c->geo_d);
     (void)hipFree(c->owned_d);
     (void)hipFree(c->slot_uid_d);
-    (void)hipFree(c->rec_d[0]);
-    (void)hipFree(c->rec_d[1]);
+    for (int l = 0; l < 2; ++l) {
+        (void)hipFree(c->va_d[l]);
+        (void)hipFree(c->vb_d[l]);
+        c->va_d[l] = c->vb_d[l] = nullptr;
+    }
+    (void)hipFree(c->cs_d);
     (void)hipFree(c->stats_d);
     c->geo_d = nullptr;
     c->owned_d = nullptr;
     c->slot_uid_d = nullptr;
-    c->rec_d[0] = c->rec_d[1] = nullptr;
+    c->cs_d = nullptr;
     c->stats_d = nullptr;
 }
 }  // namespace

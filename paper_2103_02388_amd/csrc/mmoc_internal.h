@@ -53,17 +53,26 @@ enum LaneFlag : unsigned {
     LF_NAN = 16u,
 };
 
-// Arguments of the trace kernels.  Field records are 4-wide per block slot:
-// level 0 holds (u_0 .. u_{dim-1}, ., c) at t_n (c always in component 3),
-// level 1 holds u at t_{n+1}.  T is double (FP64 path) or float (mixed path).
+// Arguments of the trace kernels.  Fields live in per-component arrays over
+// the block slots (slot = macro * npm + lattice index, macro-major, lattice
+// nodes of a macro in lexicographic order), one set per velocity level:
+//   3D float64: va = (u_x, u_y) pairs (16 B), vb = u_z (8 B)
+//   3D float32: va = (u_x, u_y, u_z) triples (12 B), vb unused
+//   2D        : va = (u_x, u_y) pairs, vb unused
+//   cs        : the scalar c at t_n
+// Small records keep the number of distinct cache lines per wave-level load
+// low, which is what the gather throughput depends on.  va[0]/vb[0] hold t_n
+// and va[1]/vb[1] t_{n+1} (the host swaps pointers between steps).
 template <typename T>
 struct TraceArgs {
     const MacroGeo* geo;
-    const uint64_t* owned;   // [n] particle table (thread order)
-    const T* rec0;           // [n_macros * npm * 4]
-    const T* rec1;           // [n_macros * npm * 4] or null when stationary
-    int64_t n;               // particles traced by this launch (threads)
-    int64_t xstride;         // total particles: stride of X and extent of c_hat
+    const uint64_t* owned;   // [n_unique] (macro, I, J, K) per DoF, unique order
+    const int32_t* order;    // [n] unique ids in lane order, or null: lane t traces DoF t
+    const T* va[2];
+    const T* vb[2];
+    const T* cs;
+    int64_t n;               // particles traced by this launch (lanes)
+    int64_t xstride;         // n_unique: stride of X and extent of c_hat
     int nm;                  // macros
     int npm;                 // lattice nodes per macro
     int nlev;                // 1 (stationary) or 2
@@ -74,9 +83,8 @@ struct TraceArgs {
     double eps_in;
     float eps32_macro;
     float eps32_micro;
-    T* c_hat;                // [n] or null
-    double* X;               // [dim][n] or null
-    const int32_t* ids;      // optional subset of particles to trace (null: all)
+    T* c_hat;                // [n_unique] or null
+    double* X;               // [dim][n_unique] or null
     unsigned long long* stats;
 };
 
@@ -86,9 +94,14 @@ hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hip
 hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
 hipError_t launch_dof_coords(int dim, int blend, const MacroGeo* geo, const uint64_t* owned,
                              int64_t n, int level_n, double* out, hipStream_t s);
-hipError_t launch_scatter_vec(int dim, const int32_t* slot_uid, int64_t nslots, const double* u,
-                              int64_t n_unique, void* rec, int fp32, hipStream_t s);
-hipError_t launch_scatter_scalar(const int32_t* slot_uid, int64_t nslots, const double* c,
-                                 void* rec, int fp32, hipStream_t s);
+// Copy of a unique-layout field into block slots: component i of DoF
+// slot_uid[slot] goes to dst[i][slot * stride[i] + off[i]] (i < ncomp).
+struct ScatterDst {
+    void* dst[3];
+    int stride[3];
+    int off[3];
+};
+hipError_t launch_scatter(int ncomp, const int32_t* slot_uid, int64_t nslots, const double* u, int64_t n_unique,
+                          const ScatterDst& d, int fp32, hipStream_t s);
 
 }  // namespace mmoc

@@ -1,0 +1,821 @@
+// mmoc_trace.hip -- the RK4 particle-trace kernels for CDNA4 (gfx950).
+//
+// One lane traces one particle through a whole MMOC advection step
+// (Sec. 2.3.1 steps (i)-(iii)): it creates the particle at its P2 DoF, runs
+// the S x 4 RK4 stages -- each a macro walk, an O(1) micro location and a P2
+// gather of both velocity levels (Sec. 2.3.2) -- accumulates the departure
+// point in float64, and evaluates the old scalar there.  Particles are
+// independent; lanes only meet in the per-wave ballots that count flagged
+// particles into the statistics.
+//
+// Memory (device resident, see mmoc_internal.h):
+//   geo    MacroGeo[n_macros], 256 B each, L2 resident
+//   owned  uint64 (macro, I, J, K) per DoF in unique order; lane t traces
+//          DoF t, so the 64 lanes of a wave run along a lattice line of one
+//          macro and their gathers hit neighbouring slots
+//   fields per-component arrays over the block slots (slot = macro * npm +
+//          lattice index): small records give few cache lines per wave-level
+//          load.  A node costs two 16-byte + two 8-byte loads (float64, two
+//          levels) or two 12-byte loads (float32, two levels).
+//   The velocity at a particle's own DoF (first stage) is its nodal value.
+//
+// Precision paths (one kernel each):
+//   fp64  every operation in float64;
+//   fp32  (mixed) the offset of a stage point from the macro origin is formed
+//         in float64, then location, shape functions and sums run in float32
+//         on float32 records; a macro decision whose smallest barycentric is
+//         within eps32_macro of zero, and a micro decision whose sorted
+//         coordinates come within eps32_micro * n of a tie, is re-taken in
+//         float64; the departure point is accumulated in float64.
+//
+// Workgroups are remapped so that each of the 8 XCDs (own L2 each) receives
+// one contiguous eighth of the particle range.
+#include "mmoc_internal.h"
+
+#include <math.h>
+
+#ifndef MMOC_TRACE_BLOCK
+#define MMOC_TRACE_BLOCK 256
+#endif
+// occupancy targets: the float64 kernel keeps its gather in flight without
+// spilling at 3 waves per SIMD, the float32 kernel fits 4
+#ifndef MMOC_WPE_FP64
+#define MMOC_WPE_FP64 3
+#endif
+#ifndef MMOC_WPE_FP32
+#define MMOC_WPE_FP32 4
+#endif
+#ifndef MMOC_XCD_REMAP
+#define MMOC_XCD_REMAP 1
+#endif
+
+namespace mmoc {
+namespace {
+
+constexpr int kTB = MMOC_TRACE_BLOCK;
+
+__device__ __forceinline__ int64_t logical_block()
+{
+#if MMOC_XCD_REMAP
+    // block b runs on XCD b % 8; give each XCD one contiguous range
+    const unsigned per = gridDim.x >> 3;
+    return (int64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+#else
+    return blockIdx.x;
+#endif
+}
+
+// ------------------------------------------------------------------ geometry
+
+template <int DIM, int BLEND>
+struct Geo64 {
+    double v0[DIM];
+    double bi[DIM][DIM];
+    double pn[3];
+    double pc;
+
+    __device__ __forceinline__ void load(const MacroGeo* __restrict__ g, int M)
+    {
+        const MacroGeo& G = g[M];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) v0[i] = G.v0[i];
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) bi[r][c] = G.binv[r * 3 + c];
+        if constexpr (BLEND) {
+            pn[0] = G.pn[0];
+            pn[1] = G.pn[1];
+            pn[2] = G.pn[2];
+            pc = G.pc;
+        }
+    }
+
+    // physical y -> offset from the macro origin in the computational domain
+    __device__ __forceinline__ void offset(const double* y, double* p) const
+    {
+        if constexpr (BLEND) {
+            // Phi^-1(z) = z c |z| / (n.z)
+            const double nz = pn[0] * y[0] + pn[1] * y[1] + pn[2] * y[2];
+            const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+            const double f = pc * r / nz;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) p[i] = fma(y[i], f, -v0[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) p[i] = y[i] - v0[i];
+        }
+    }
+
+    // reference coordinates s of y, returns lambda_0 = 1 - sum s
+    __device__ __forceinline__ double ref(const double* y, double* s) const
+    {
+        double p[DIM];
+        offset(y, p);
+        double sum = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) acc = fma(bi[a][i], p[i], acc);
+            s[a] = acc;
+            sum += acc;
+        }
+        return 1.0 - sum;
+    }
+};
+
+template <int DIM, typename R>
+__device__ __forceinline__ R lam_min(R l0, const R* s)
+{
+    R m = l0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) m = fmin(m, s[a]);
+    return m;
+}
+
+// Macro walk from M (Sec. 2.3.2: search the neighbourhood of the macro that
+// held the previous evaluation).  Accept when min lambda >= -eps; otherwise
+// hop across the face with the most negative lambda among faces that have a
+// neighbour (ties: lowest face).  No such face: the point is outside the
+// domain and stays in M.  After max_hops hops: brute force (argmax over
+// macros of min lambda, ties: lowest macro).  Out of line and scalar-only so
+// that the hot loop never spills; returns the macro in bits 0-26 and lane
+// flags above.
+template <int DIM, int BLEND>
+__device__ __noinline__ unsigned walk64(const MacroGeo* __restrict__ geo, int nm, int max_hops, double eps, int M,
+                                        double y0, double y1, double y2)
+{
+    const double y[3] = {y0, y1, y2};
+    double s[DIM];
+    unsigned flags = 0;
+    Geo64<DIM, BLEND> G;
+    G.load(geo, M);
+    for (int hop = 0;; ++hop) {
+        const double l0 = G.ref(y, s);
+        if (lam_min<DIM, double>(l0, s) >= -eps) return (unsigned)M | (flags << 27);
+        const int32_t* nb = geo[M].nbr;
+        int kb = -1, nk = -1;
+        double lb = 0.0;
+#pragma unroll
+        for (int k = 0; k <= DIM; ++k) {
+            const double lk = k == 0 ? l0 : s[k - 1];
+            if (lk < -eps) {
+                const int q = nb[k];
+                if (q >= 0 && (kb < 0 || lk < lb)) {
+                    kb = k;
+                    lb = lk;
+                    nk = q;
+                }
+            }
+        }
+        if (kb < 0) return (unsigned)M | ((flags | LF_OUTSIDE) << 27);
+        if (hop >= max_hops) break;
+        if (hop >= 1) flags |= LF_MULTIHOP;
+        M = nk;
+        G.load(geo, M);
+    }
+    flags |= LF_BRUTE;
+    int best = 0;
+    double bestv = -INFINITY;
+    for (int q = 0; q < nm; ++q) {
+        G.load(geo, q);
+        const double ll = G.ref(y, s);
+        const double v = lam_min<DIM, double>(ll, s);
+        if (v > bestv) {
+            bestv = v;
+            best = q;
+        }
+    }
+    if (bestv < -eps) flags |= LF_OUTSIDE;
+    return (unsigned)best | (flags << 27);
+}
+
+// ------------------------------------------------------ micro element + P2
+
+template <int DIM, typename R>
+struct Stencil {
+    static constexpr int NN = (DIM + 1) * (DIM + 2) / 2;
+    int idx[NN];  // lattice index of the P2 nodes: vertices 0..DIM, then edges (a<b)
+    R phi[NN];    // shape function values
+};
+
+__device__ __forceinline__ int tri_n(int x) { return (x * (x + 1)) >> 1; }
+__device__ __forceinline__ int tet_n(int x) { return (x * (x + 1) * (x + 2)) / 6; }
+
+// O(1) micro location in the Freudenthal lattice of the macro's Kuhn
+// coordinates w (w_d = s_d, w_a = s_a + w_{a+1}), then the P2 shape
+// functions at the (possibly unclamped) point.  A point outside the macro
+// selects its element from the clamped, renormalised barycentrics and is
+// evaluated by extrapolating that element.  Returns the smallest distance of
+// the selection coordinates W = n w from a tie (an integer, or another
+// coordinate), which the mixed-precision path compares with its band.
+template <int DIM, typename R>
+__device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM, R>& st)
+{
+    R ssel[DIM];
+    if (lmin >= R(0)) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) ssel[a] = s[a];
+    } else {
+        R sum = fmax(l0, R(0));
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) sum += fmax(s[a], R(0));
+        const R inv = R(1) / sum;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) ssel[a] = fmax(s[a], R(0)) * inv;
+    }
+    const R dn = (R)n;
+    R W[DIM], Wu[DIM];
+    W[DIM - 1] = ssel[DIM - 1];
+    Wu[DIM - 1] = s[DIM - 1];
+#pragma unroll
+    for (int a = DIM - 2; a >= 0; --a) {
+        W[a] = ssel[a] + W[a + 1];
+        Wu[a] = s[a] + Wu[a + 1];
+    }
+    int k[3] = {0, 0, 0};
+    R f[DIM], fu[DIM];
+    R gap = R(1);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        W[i] *= dn;
+        Wu[i] *= dn;
+        const R kc = floor(fmin(fmax(W[i], R(0)), dn - R(1)));
+        k[i] = (int)kc;
+        f[i] = W[i] - kc;
+        fu[i] = Wu[i] - kc;
+        gap = fmin(gap, fmin(fabs(f[i]), fabs(R(1) - f[i])));
+    }
+    // rank of each axis in the descending order of f (ties: lower axis first)
+    int r[3] = {0, 0, 0};
+    R g[DIM];
+    if constexpr (DIM == 3) {
+        r[0] = (f[1] > f[0]) + (f[2] > f[0]);
+        r[1] = (f[0] >= f[1]) + (f[2] > f[1]);
+        r[2] = (f[0] >= f[2]) + (f[1] >= f[2]);
+        g[0] = r[0] == 0 ? fu[0] : (r[1] == 0 ? fu[1] : fu[2]);
+        g[1] = r[0] == 1 ? fu[0] : (r[1] == 1 ? fu[1] : fu[2]);
+        g[2] = r[0] == 2 ? fu[0] : (r[1] == 2 ? fu[1] : fu[2]);
+        gap = fmin(gap, fmin(fabs(f[0] - f[1]), fmin(fabs(f[0] - f[2]), fabs(f[1] - f[2]))));
+    } else {
+        r[0] = f[1] > f[0];
+        r[1] = f[0] >= f[1];
+        g[0] = r[0] == 0 ? fu[0] : fu[1];
+        g[1] = r[0] == 1 ? fu[0] : fu[1];
+        gap = fmin(gap, fabs(f[0] - f[1]));
+    }
+    R mu[DIM + 1];
+    mu[0] = R(1) - g[0];
+#pragma unroll
+    for (int a = 1; a < DIM; ++a) mu[a] = g[a - 1] - g[a];
+    mu[DIM] = g[DIM - 1];
+    // micro vertex a = k + sum of the first a axes in rank order, i.e.
+    // V_a[i] = k_i + [r_i < a]; node (a,b) sits at V_a + V_b in the P2
+    // lattice, 2k + delta with delta_i = [r_i < a] + [r_i < b] in {0,1,2}
+    const int I0 = 2 * k[0], J0 = 2 * k[1], K0 = 2 * k[2];
+    int TI[3], TJ[3];
+    if constexpr (DIM == 3) {
+        TI[0] = tet_n(I0);
+        TI[1] = TI[0] + tri_n(I0 + 1);
+        TI[2] = TI[1] + tri_n(I0 + 2);
+        TJ[0] = tri_n(J0);
+        TJ[1] = TJ[0] + J0 + 1;
+        TJ[2] = TJ[1] + J0 + 2;
+    } else {
+        TI[0] = tri_n(I0);
+        TI[1] = TI[0] + I0 + 1;
+        TI[2] = TI[1] + I0 + 2;
+        TJ[0] = J0;
+        TJ[1] = J0 + 1;
+        TJ[2] = J0 + 2;
+    }
+    auto node = [&](int a, int b) {
+        const int dI = (r[0] < a) + (r[0] < b);
+        const int dJ = (r[1] < a) + (r[1] < b);
+        if constexpr (DIM == 3) {
+            const int dK = (r[2] < a) + (r[2] < b);
+            return (dI == 0 ? TI[0] : (dI == 1 ? TI[1] : TI[2])) + (dJ == 0 ? TJ[0] : (dJ == 1 ? TJ[1] : TJ[2])) +
+                   K0 + dK;
+        } else {
+            return (dI == 0 ? TI[0] : (dI == 1 ? TI[1] : TI[2])) + (dJ == 0 ? TJ[0] : (dJ == 1 ? TJ[1] : TJ[2]));
+        }
+    };
+    int c = 0;
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        st.idx[c] = node(a, a);
+        st.phi[c] = mu[a] * fma(R(2), mu[a], R(-1));
+        ++c;
+    }
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+        for (int b = a + 1; b <= DIM; ++b) {
+            st.idx[c] = node(a, b);
+            st.phi[c] = R(4) * mu[a] * mu[b];
+            ++c;
+        }
+    return gap;
+}
+
+// Particle creation (step (i)): physical position of lattice node (I, J, K)
+// of macro M, x = Phi(v0 + B s), s = (I - J, J - K, K) / m.
+template <int DIM, int BLEND>
+__device__ __forceinline__ void dof_position(const MacroGeo* __restrict__ geo, uint64_t e, int level_n, int& M,
+                                             double* x)
+{
+    M = (int)(e >> 36);
+    const int I = (int)((e >> 24) & 0xfffu), J = (int)((e >> 12) & 0xfffu), K = (int)(e & 0xfffu);
+    const double invm = 1.0 / (double)(2 * level_n);  // exact: m is a power of two
+    double s[3];
+    if constexpr (DIM == 2) {
+        s[0] = (double)(I - J) * invm;
+        s[1] = (double)J * invm;
+    } else {
+        s[0] = (double)(I - J) * invm;
+        s[1] = (double)(J - K) * invm;
+        s[2] = (double)K * invm;
+    }
+    const MacroGeo& G = geo[M];
+    double p[3];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        double acc = G.v0[i];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) acc = fma(G.B[i * 3 + a], s[a], acc);
+        p[i] = acc;
+    }
+    if constexpr (BLEND) {
+        const double nx = G.pn[0] * p[0] + G.pn[1] * p[1] + G.pn[2] * p[2];
+        const double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        const double f = nx / (G.pc * r);
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) x[i] = p[i] * f;
+    } else {
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) x[i] = p[i];
+    }
+}
+
+// ------------------------------------------------------------------ gathers
+
+// load of a V from a uniform base plus a 32-bit byte offset (the SGPR-base
+// addressing form: no 64-bit address arithmetic per load)
+template <typename V, typename T>
+__device__ __forceinline__ V ldv(const T* __restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+struct alignas(4) F3 {
+    float x, y, z;
+};
+
+// velocity vector of one level at slot q
+template <int DIM, typename T>
+__device__ __forceinline__ void load_vec(const TraceArgs<T>& A, int L, uint32_t q, T* u)
+{
+    if constexpr (sizeof(T) == 8) {
+        const double2 xy = ldv<double2>(A.va[L], q * 16u);
+        u[0] = xy.x;
+        u[1] = xy.y;
+        if constexpr (DIM == 3) u[2] = ldv<double>(A.vb[L], q * 8u);
+    } else if constexpr (DIM == 3) {
+        const F3 v = ldv<F3>(A.va[L], q * 12u);
+        u[0] = v.x;
+        u[1] = v.y;
+        u[2] = v.z;
+    } else {
+        const float2 xy = ldv<float2>(A.va[L], q * 8u);
+        u[0] = xy.x;
+        u[1] = xy.y;
+    }
+}
+
+// Velocity at a stage point: P2 sums of both levels weighted (1 - theta,
+// theta), or the single level of a stationary run.
+template <int DIM, int NLEV, typename T, typename R>
+__device__ __forceinline__ void gather_vel(const TraceArgs<T>& A, uint32_t mbase, const Stencil<DIM, R>& st, R theta,
+                                           R* k)
+{
+    constexpr int NN = Stencil<DIM, R>::NN;
+    R ua[DIM], ub[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        ua[i] = R(0);
+        ub[i] = R(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NN; ++q) {
+        const uint32_t slot = mbase + (uint32_t)st.idx[q];
+        T a[DIM];
+        load_vec<DIM, T>(A, 0, slot, a);
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) ua[i] = fma(st.phi[q], (R)a[i], ua[i]);
+        if constexpr (NLEV == 2) {
+            T b[DIM];
+            load_vec<DIM, T>(A, 1, slot, b);
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) ub[i] = fma(st.phi[q], (R)b[i], ub[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) k[i] = NLEV == 2 ? (R(1) - theta) * ua[i] + theta * ub[i] : ua[i];
+}
+
+// velocity at a lattice node: the nodal values (P2 interpolation is the
+// identity there)
+template <int DIM, int NLEV, typename T, typename R>
+__device__ __forceinline__ void nodal_vel(const TraceArgs<T>& A, uint32_t slot, R theta, R* k)
+{
+    T a[DIM];
+    load_vec<DIM, T>(A, 0, slot, a);
+    if constexpr (NLEV == 2) {
+        T b[DIM];
+        load_vec<DIM, T>(A, 1, slot, b);
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) k[i] = (R(1) - theta) * (R)a[i] + theta * (R)b[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) k[i] = (R)a[i];
+    }
+}
+
+template <int DIM, typename T, typename R>
+__device__ __forceinline__ R gather_scalar(const TraceArgs<T>& A, uint32_t mbase, const Stencil<DIM, R>& st)
+{
+    constexpr int NN = Stencil<DIM, R>::NN;
+    R acc = R(0);
+#pragma unroll
+    for (int q = 0; q < NN; ++q)
+        acc = fma(st.phi[q], (R)ldv<T>(A.cs, (mbase + (uint32_t)st.idx[q]) * (uint32_t)sizeof(T)), acc);
+    return acc;
+}
+
+template <int DIM>
+__device__ __forceinline__ int own_lat_idx(uint64_t e)
+{
+    const int I = (int)((e >> 24) & 0xfffu), J = (int)((e >> 12) & 0xfffu), K = (int)(e & 0xfffu);
+    if constexpr (DIM == 2) return tri_n(I) + J;
+    else return tet_n(I) + tri_n(J) + K;
+}
+
+__device__ __forceinline__ void count_flags(unsigned long long* stats, bool active, unsigned flags)
+{
+    const unsigned long long nact = __popcll(__ballot(active));
+    const unsigned long long no = __popcll(__ballot((flags & LF_OUTSIDE) != 0));
+    const unsigned long long nm = __popcll(__ballot((flags & LF_MULTIHOP) != 0));
+    const unsigned long long nb = __popcll(__ballot((flags & LF_BRUTE) != 0));
+    const unsigned long long nt = __popcll(__ballot((flags & LF_TIEBAND) != 0));
+    const unsigned long long nn = __popcll(__ballot((flags & LF_NAN) != 0));
+    if ((threadIdx.x & 63) == 0) {
+        if (nact) atomicAdd(stats + ST_PARTICLES, nact);
+        if (no) atomicAdd(stats + ST_OUTSIDE, no);
+        if (nm) atomicAdd(stats + ST_MULTIHOP, nm);
+        if (nb) atomicAdd(stats + ST_BRUTE, nb);
+        if (nt) atomicAdd(stats + ST_TIEBAND, nt);
+        if (nn) atomicAdd(stats + ST_NAN, nn);
+    }
+}
+
+// --------------------------------------------------------------- fp64 trace
+
+template <int DIM, int NLEV, int BLEND>
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP64)))
+void trace_fp64_kernel(const TraceArgs<double> A)
+{
+    const int64_t t = logical_block() * kTB + threadIdx.x;
+    const bool active = t < A.n;
+    unsigned flags = 0;
+    if (active) {
+        const int64_t pid = A.order ? (int64_t)A.order[t] : t;
+        const uint64_t e = A.owned[pid];
+        int M;
+        double Y[DIM];
+        dof_position<DIM, BLEND>(A.geo, e, A.level_n, M, Y);
+        Geo64<DIM, BLEND> G;
+        G.load(A.geo, M);
+        uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
+        const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
+        const double h = A.dt / (double)A.substeps;
+        const double hh = 0.5 * h;
+        const double h6 = h / 6.0;
+        const double invS = 1.0 / (double)A.substeps;
+        double s[DIM], l0, lmin;
+        Stencil<DIM, double> st;
+#pragma unroll 1
+        for (int j = 0; j < A.substeps; ++j) {
+            double ks[DIM], acc[DIM], y[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) y[i] = Y[i];
+#pragma unroll 1
+            for (int stg = 0; stg < 4; ++stg) {
+                // stage time theta = 1 - (j + a_s)/S, a_s = 0, 1/2, 1/2, 1
+                const double as = stg == 0 ? 0.0 : (stg == 3 ? 1.0 : 0.5);
+                const double theta = 1.0 - ((double)j + as) * invS;
+                if (j == 0 && stg == 0) {
+                    // the particle sits on its own DoF
+                    nodal_vel<DIM, NLEV, double, double>(A, own_slot, theta, ks);
+                } else {
+                    l0 = G.ref(y, s);
+                    lmin = lam_min<DIM, double>(l0, s);
+                    if (lmin < -A.eps_in) {
+                        const unsigned r = walk64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, y[0], y[1],
+                                                             DIM == 3 ? y[DIM - 1] : 0.0);
+                        flags |= r >> 27;
+                        const int M2 = (int)(r & ((1u << 27) - 1));
+                        if (M2 != M) {
+                            M = M2;
+                            G.load(A.geo, M);
+                            mbase = (uint32_t)M * (uint32_t)A.npm;
+                        }
+                        l0 = G.ref(y, s);
+                        lmin = lam_min<DIM, double>(l0, s);
+                    }
+                    micro<DIM, double>(s, l0, lmin, A.level_n, st);
+                    gather_vel<DIM, NLEV, double, double>(A, mbase, st, theta, ks);
+                }
+                // k1 + 2 k2 + 2 k3 + k4 accumulated in stage order; next stage point
+                const double wst = (stg == 0 || stg == 3) ? 1.0 : 2.0;
+                const double cnext = stg == 2 ? h : hh;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    acc[i] = stg == 0 ? ks[i] : fma(wst, ks[i], acc[i]);
+                    y[i] = Y[i] - cnext * ks[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - h6 * acc[i];
+        }
+        // step (iii): the scalar at the departure point
+        l0 = G.ref(Y, s);
+        lmin = lam_min<DIM, double>(l0, s);
+        if (lmin < -A.eps_in) {
+            const unsigned r =
+                walk64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, Y[0], Y[1], DIM == 3 ? Y[DIM - 1] : 0.0);
+            flags |= r >> 27;
+            const int M2 = (int)(r & ((1u << 27) - 1));
+            if (M2 != M) {
+                M = M2;
+                G.load(A.geo, M);
+                mbase = (uint32_t)M * (uint32_t)A.npm;
+            }
+            l0 = G.ref(Y, s);
+            lmin = lam_min<DIM, double>(l0, s);
+        }
+        micro<DIM, double>(s, l0, lmin, A.level_n, st);
+        const double v = gather_scalar<DIM, double, double>(A, mbase, st);
+        bool bad = v != v;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) bad |= Y[i] != Y[i];
+        if (bad) flags |= LF_NAN;
+        if (A.c_hat) A.c_hat[pid] = v;
+        if (A.X) {
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) A.X[(int64_t)i * A.xstride + pid] = Y[i];
+        }
+    }
+    count_flags(A.stats, active, flags);
+}
+
+// --------------------------------------------------------- fp32 mixed trace
+
+template <int DIM, int BLEND>
+struct Geo32 {
+    double v0[DIM];
+    float bi[DIM][DIM];
+
+    __device__ __forceinline__ void load(const MacroGeo* __restrict__ g, int M)
+    {
+        const MacroGeo& G = g[M];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) v0[i] = G.v0[i];
+#pragma unroll
+        for (int r = 0; r < DIM; ++r)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) bi[r][c] = G.binvf[r * 3 + c];
+    }
+};
+
+// Reference coordinates in float32: the offset from the macro origin is
+// formed in float64 (the only float64 work of an ordinary stage), then
+// rounded and mapped with the float32 inverse.
+template <int DIM, int BLEND>
+__device__ __forceinline__ float ref32(const Geo32<DIM, BLEND>& G, const MacroGeo* __restrict__ geo, int M,
+                                       const double* y, float* s)
+{
+    float p[DIM];
+    if constexpr (BLEND) {
+        const MacroGeo& Gm = geo[M];
+        const double nz = Gm.pn[0] * y[0] + Gm.pn[1] * y[1] + Gm.pn[2] * y[2];
+        const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+        const double f = Gm.pc * r / nz;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) p[i] = (float)fma(y[i], f, -G.v0[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) p[i] = (float)(y[i] - G.v0[i]);
+    }
+    float sum = 0.0f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) acc = fmaf(G.bi[a][i], p[i], acc);
+        s[a] = acc;
+        sum += acc;
+    }
+    return 1.0f - sum;
+}
+
+// The float64 re-evaluation of one location: with `walk`, the macro walk in
+// float64 (a macro tie or a macro change), then the micro element in float64
+// (shape functions handed back in float32).  Out of line: it runs for a
+// small fraction of the evaluations and must not cost the hot loop registers.
+template <int DIM, int BLEND>
+__device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int nm, int max_hops, double eps, int M,
+                                          int level_n, int walk, double y0, double y1, double y2,
+                                          Stencil<DIM, float>* out)
+{
+    unsigned r = (unsigned)M;
+    if (walk) r = walk64<DIM, BLEND>(geo, nm, max_hops, eps, M, y0, y1, y2);
+    const int M2 = (int)(r & ((1u << 27) - 1));
+    Geo64<DIM, BLEND> G;
+    G.load(geo, M2);
+    const double y[3] = {y0, y1, y2};
+    double s[DIM];
+    const double l0 = G.ref(y, s);
+    const double lmin = lam_min<DIM, double>(l0, s);
+    Stencil<DIM, double> st;
+    micro<DIM, double>(s, l0, lmin, level_n, st);
+#pragma unroll
+    for (int q = 0; q < Stencil<DIM, double>::NN; ++q) {
+        out->idx[q] = st.idx[q];
+        out->phi[q] = (float)st.phi[q];
+    }
+    return r;
+}
+
+// Location of a stage point in float32.  A macro decision that float32
+// cannot take with certainty -- the smallest barycentric within eps32_macro
+// of zero on a face that has a neighbour, or a macro change -- is re-taken
+// in float64, and so is a micro decision within eps32_micro * n of a tie.
+// Near a boundary face there is no second macro to choose: the point stays,
+// and its element is selected from the clamped barycentrics as in float64.
+template <int DIM, int BLEND>
+__device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, Geo32<DIM, BLEND>& G, uint32_t& mbase,
+                                         const double* y, Stencil<DIM, float>& st, unsigned& flags)
+{
+    float s[DIM];
+    const float l0 = ref32<DIM, BLEND>(G, A.geo, M, y, s);
+    const float lmin = lam_min<DIM, float>(l0, s);
+    bool macro_redo = lmin < A.eps32_macro;
+    if (macro_redo && lmin > -A.eps32_macro) {
+        // inside the band: only faces with a neighbour carry a decision
+        const int32_t* nb = A.geo[M].nbr;
+        bool interior = false;
+#pragma unroll
+        for (int k = 0; k <= DIM; ++k) {
+            const float lk = k == 0 ? l0 : s[k - 1];
+            interior |= (lk < A.eps32_macro) && (nb[k] >= 0);
+        }
+        macro_redo = interior;
+    }
+    bool redo = macro_redo;
+    if (!macro_redo) {
+        const float gap = micro<DIM, float>(s, l0, lmin, A.level_n, st);
+        redo = gap < A.eps32_micro * (float)A.level_n;
+    }
+    if (redo) {
+        if (!macro_redo || lmin > -A.eps32_macro) flags |= LF_TIEBAND;
+        Stencil<DIM, float> s64;
+        const unsigned r = locate64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, A.level_n, macro_redo, y[0],
+                                                y[1], DIM == 3 ? y[DIM - 1] : 0.0, &s64);
+        flags |= r >> 27;
+        const int M2 = (int)(r & ((1u << 27) - 1));
+        if (M2 != M) {
+            M = M2;
+            G.load(A.geo, M);
+            mbase = (uint32_t)M * (uint32_t)A.npm;
+        }
+        st = s64;
+    }
+}
+
+template <int DIM, int NLEV, int BLEND>
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP32)))
+void trace_fp32_kernel(const TraceArgs<float> A)
+{
+    const int64_t t = logical_block() * kTB + threadIdx.x;
+    const bool active = t < A.n;
+    unsigned flags = 0;
+    if (active) {
+        const int64_t pid = A.order ? (int64_t)A.order[t] : t;
+        const uint64_t e = A.owned[pid];
+        int M;
+        double Y[DIM];
+        dof_position<DIM, BLEND>(A.geo, e, A.level_n, M, Y);
+        Geo32<DIM, BLEND> G;
+        G.load(A.geo, M);
+        uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
+        const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
+        const double hd = A.dt / (double)A.substeps;
+        const float h = (float)hd;
+        const float hh = 0.5f * h;
+        const float h6 = h / 6.0f;
+        const float invS = 1.0f / (float)A.substeps;
+        Stencil<DIM, float> st;
+#pragma unroll 1
+        for (int j = 0; j < A.substeps; ++j) {
+            float ks[DIM], acc[DIM];
+            double y[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) y[i] = Y[i];
+#pragma unroll 1
+            for (int stg = 0; stg < 4; ++stg) {
+                const float as = stg == 0 ? 0.0f : (stg == 3 ? 1.0f : 0.5f);
+                const float theta = 1.0f - ((float)j + as) * invS;
+                if (j == 0 && stg == 0) {
+                    nodal_vel<DIM, NLEV, float, float>(A, own_slot, theta, ks);
+                } else {
+                    locate32<DIM, BLEND>(A, M, G, mbase, y, st, flags);
+                    gather_vel<DIM, NLEV, float, float>(A, mbase, st, theta, ks);
+                }
+                const float wst = (stg == 0 || stg == 3) ? 1.0f : 2.0f;
+                const float cnext = stg == 2 ? h : hh;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    acc[i] = stg == 0 ? ks[i] : fmaf(wst, ks[i], acc[i]);
+                    y[i] = Y[i] - (double)(cnext * ks[i]);
+                }
+            }
+            // departure point accumulated in float64
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - (double)(h6 * acc[i]);
+        }
+        locate32<DIM, BLEND>(A, M, G, mbase, Y, st, flags);
+        const float v = gather_scalar<DIM, float, float>(A, mbase, st);
+        bool bad = v != v;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) bad |= Y[i] != Y[i];
+        if (bad) flags |= LF_NAN;
+        if (A.c_hat) A.c_hat[pid] = v;
+        if (A.X) {
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) A.X[(int64_t)i * A.xstride + pid] = Y[i];
+        }
+    }
+    count_flags(A.stats, active, flags);
+}
+
+inline unsigned grid_xcd(int64_t n)
+{
+    int64_t b = (n + kTB - 1) / kTB;
+    b = (b + 7) / 8 * 8;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid(grid_xcd(a.n)), block(kTB);
+    const bool st = a.nlev == 1;
+    if (dim == 2 && !blend) {
+        if (st) trace_fp64_kernel<2, 1, 0><<<grid, block, 0, s>>>(a);
+        else trace_fp64_kernel<2, 2, 0><<<grid, block, 0, s>>>(a);
+    } else if (dim == 3 && !blend) {
+        if (st) trace_fp64_kernel<3, 1, 0><<<grid, block, 0, s>>>(a);
+        else trace_fp64_kernel<3, 2, 0><<<grid, block, 0, s>>>(a);
+    } else if (dim == 3 && blend) {
+        if (st) trace_fp64_kernel<3, 1, 1><<<grid, block, 0, s>>>(a);
+        else trace_fp64_kernel<3, 2, 1><<<grid, block, 0, s>>>(a);
+    } else {
+        return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid(grid_xcd(a.n)), block(kTB);
+    const bool st = a.nlev == 1;
+    if (dim == 2 && !blend) {
+        if (st) trace_fp32_kernel<2, 1, 0><<<grid, block, 0, s>>>(a);
+        else trace_fp32_kernel<2, 2, 0><<<grid, block, 0, s>>>(a);
+    } else if (dim == 3 && !blend) {
+        if (st) trace_fp32_kernel<3, 1, 0><<<grid, block, 0, s>>>(a);
+        else trace_fp32_kernel<3, 2, 0><<<grid, block, 0, s>>>(a);
+    } else if (dim == 3 && blend) {
+        if (st) trace_fp32_kernel<3, 1, 1><<<grid, block, 0, s>>>(a);
+        else trace_fp32_kernel<3, 2, 1><<<grid, block, 0, s>>>(a);
+    } else {
+        return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mmoc

@@ -51,8 +51,8 @@ def test_argument_and_state_errors():
         tr.trace_step(0.1, 4, c, X)
     assert e.value.status == -3
     u = torch.zeros((3, N), dtype=torch.float64, device=dev)
-    tr.set_velocity(0, u)
     tr.set_stationary(True)
+    tr.set_velocity(0, u)
     with pytest.raises(mmoc.MMOCError) as e:
         tr.trace_step(0.1, 4, c, X)  # scalar missing
     assert e.value.status == -3

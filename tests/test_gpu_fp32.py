@@ -1,0 +1,142 @@
+"""Mixed-precision tracer (float32 stages, float64 tie-break and departure
+accumulation) on the GPU vs the float64 CPU oracle.
+
+Tolerances: departure points 1e-5 relative (max |X - X_ref| / max(1, max
+|X_ref|)).  chat inherits the departure error through the scalar's gradient
+(|chat - chat_ref| <= L |X - X_ref| + float32 interpolation rounding), so the
+chat bound is 1e-5 * max(1, L) + 1e-6 relative, with L the largest nodal
+difference quotient of the scalar over one P2 lattice spacing.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2103_02388_amd import mmoc
+from paper_2103_02388_amd import workloads as W
+
+from gpu_helpers import Pair, rel_c, rel_x
+
+pytestmark = pytest.mark.gpu
+TOL_X = 1e-5
+
+
+def lipschitz(pair):
+    """max |grad c| estimated from the scalar at the DoFs: nodal differences
+    over the lattice spacing along each axis of the (Kuhn) grid."""
+    x = pair.xc
+    c = pair.cc
+    m = pair.om.m
+    h = 1.0 / m
+    key = np.rint(x * m).astype(np.int64)
+    L = 0.0
+    if pair.wl.blend == 0 and np.abs(x * m - key).max() < 1e-9:
+        grid = {}
+        for i in range(x.shape[1]):
+            grid[tuple(key[:, i])] = c[i]
+        for i in range(0, x.shape[1], max(1, x.shape[1] // 20000)):
+            k0 = tuple(key[:, i])
+            for d in range(x.shape[0]):
+                k1 = list(k0)
+                k1[d] += 1
+                k1 = tuple(k1)
+                if k1 in grid:
+                    L = max(L, abs(grid[k1] - grid[k0]) / h)
+    return L
+
+
+def chat_tol(L):
+    return TOL_X * max(1.0, L) + 1e-6
+
+
+def check(pair, ch, X, chr_, Xr, L):
+    ex, ec = rel_x(X, Xr), rel_c(ch, chr_)
+    assert ex <= TOL_X, ex
+    assert ec <= chat_tol(L) / max(np.abs(chr_).max(), 1e-300), (ec, L)
+    return ex, ec
+
+
+@pytest.mark.parametrize("step,S", [(7, 4), (0, 1), (19, 4)])
+def test_swirl3d_full_size_fp32(step, S):
+    wl = W.swirl3d()
+    p = Pair(wl, precision=mmoc.MMOC_FP32_MIXED)
+    t_n = step * wl.dt
+    p.set_fields(t_n, wl.dt, False)
+    p.tr.reset_stats()
+    ch, X = p.gpu_step(wl.dt, S)
+    chr_, Xr, _ = p.oracle_step(wl.dt, S, threads=8)
+    ex, ec = check(p, ch, X, chr_, Xr, lipschitz(p))
+    st = p.tr.stats()
+    assert st["n_particles"] == p.tr.N and st["n_nan"] == 0
+    # the float64 tie-break (macro band) touches a small fraction of the particles
+    assert st["n_tieband"] < 0.2 * p.tr.N
+    print("fp32 swirl step %d S=%d: X %.2e chat %.2e tieband %.3f" % (step, S, ex, ec, st["n_tieband"] / p.tr.N))
+
+
+def test_rotation2d_full_size_fp32():
+    wl = W.rotation2d()
+    p = Pair(wl, precision=mmoc.MMOC_FP32_MIXED)
+    p.set_fields(0.0, wl.dt, True)
+    ch, X = p.gpu_step(wl.dt, wl.substeps)
+    chr_, Xr, _ = p.oracle_step(wl.dt, wl.substeps)
+    check(p, ch, X, chr_, Xr, lipschitz(p))
+
+
+def test_small_meshes_and_large_steps_fp32():
+    for level in (0, 1, 2, 3):
+        for wl in (W.rotation2d(), W.swirl3d()):
+            p = Pair(wl, level=level, precision=mmoc.MMOC_FP32_MIXED)
+            p.set_fields(0.2, wl.dt * 3, wl.stationary)
+            ch, X = p.gpu_step(wl.dt * 3, 3)
+            chr_, Xr, _ = p.oracle_step(wl.dt * 3, 3)
+            check(p, ch, X, chr_, Xr, lipschitz(p))
+
+
+def test_tie_band_widths():
+    """No band, the default band and a band that sends every location to
+    float64 all stay within tolerance; the wide band matches float64 closely."""
+    wl = W.swirl3d()
+    res = {}
+    for name, em, eu in (("none", 0.0, 0.0), ("default", None, None), ("micro", 4e-6, 2.0 ** -18),
+                         ("all", 1e9, 1e9)):
+        opt = mmoc.mmoc_default_options()
+        if em is not None:
+            opt.eps32_macro = em
+            opt.eps32_micro = eu
+        p = Pair(wl, level=4, precision=mmoc.MMOC_FP32_MIXED, options=opt)
+        p.set_fields(0.6, wl.dt, False)
+        p.tr.reset_stats()
+        ch, X = p.gpu_step(wl.dt, 4)
+        chr_, Xr, _ = p.oracle_step(wl.dt, 4)
+        ex, ec = check(p, ch, X, chr_, Xr, lipschitz(p))
+        res[name] = (ex, p.tr.stats()["n_tieband"])
+    assert res["none"][1] == 0
+    assert res["micro"][1] > res["default"][1]
+    assert res["all"][1] == p.tr.N
+
+
+def test_shell_fp32():
+    wl = W.shell3d(level=1)
+    p = Pair(wl, level=1, precision=mmoc.MMOC_FP32_MIXED)
+    p.set_fields(0.0, wl.dt, True)
+    ch, X = p.gpu_step(wl.dt, 4)
+    chr_, Xr, _ = p.oracle_step(wl.dt, 4)
+    ex = rel_x(X, Xr)
+    assert ex <= TOL_X
+    # the step scalar has O(1) jumps across r = 0.8: compare where the oracle's
+    # stencil does not straddle the jump, i.e. at departure points whose
+    # radius is not within one micro cell of 0.8
+    r = np.linalg.norm(Xr, axis=0)
+    far = np.abs(r - 0.8) > 0.45 / 4 / 2
+    assert np.abs(ch[far] - chr_[far]).max() <= 1e-4
+
+
+def test_plume3d_full_size_sampled_fp32():
+    wl = W.plume3d()
+    p = Pair(wl, precision=mmoc.MMOC_FP32_MIXED)
+    p.set_fields(120 * wl.dt, wl.dt, False)
+    ch, X = p.gpu_step(wl.dt, 4)
+    ids = np.sort(np.random.default_rng(13).choice(p.tr.N, 3000, replace=False))
+    chr_, Xr, _ = p.oracle_step(wl.dt, 4, ids=ids, threads=8)
+    assert rel_x(X[:, ids], Xr) <= TOL_X
+    # exp(-10 z): |grad c| <= 10
+    assert np.abs(ch[ids] - chr_).max() <= chat_tol(10.0)

@@ -103,10 +103,35 @@ def test_stationary_equals_two_identical_levels():
     p = Pair(wl, level=3)
     p.set_fields(0.4, wl.dt, True)
     ch1, X1 = p.gpu_step(wl.dt, 4)
-    p.tr.set_stationary(False)
+    p.tr.set_stationary(False)  # new record layout: every field is set again
+    with pytest.raises(mmoc.MMOCError):
+        p.tr.trace_step(wl.dt, 4)
+    p.tr.set_velocity(0, p.u0g)
     p.tr.set_velocity(1, p.u0g)
+    p.tr.set_scalar(p.cg)
     ch2, X2 = p.gpu_step(wl.dt, 4)
     assert rel_x(X1, X2) <= 1e-15 and rel_c(ch1, ch2) <= 1e-15
+
+
+@pytest.mark.parametrize("precision", [mmoc.MMOC_FP64, mmoc.MMOC_FP32_MIXED])
+def test_level_swap_equals_fresh_upload(precision):
+    """After a swap the old level 1 acts as level 0: the same step, to the
+    last bits (the time weights meet the two sums in the other order), as a
+    context whose level 0 was uploaded directly."""
+    wl = W.swirl3d()
+    a = Pair(wl, level=3, precision=precision)
+    b = Pair(wl, level=3, precision=precision)
+    t0 = 0.45
+    a.set_fields(t0 - wl.dt, wl.dt, False)
+    a.gpu_step(wl.dt, 4)
+    a.tr.swap_levels()
+    u2 = field_gpu(wl.velocity, a.xg, t0 + wl.dt)
+    a.tr.set_velocity(1, u2)
+    b.set_fields(t0, wl.dt, False)
+    A = a.gpu_step(wl.dt, 4)
+    B = b.gpu_step(wl.dt, 4)
+    tol = 1e-14 if precision == mmoc.MMOC_FP64 else 1e-6
+    assert rel_x(A[1], B[1]) <= tol and rel_c(A[0], B[0]) <= tol
 
 
 def test_multi_step_chain_with_level_swap():
