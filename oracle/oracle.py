@@ -272,3 +272,41 @@ def p2_mass_ref(dim):
 
 def lat_idx(dim, I, J, K=0):
     return int(lib().orc_lat_idx(int(dim), int(I), int(J), int(K)))
+
+
+# ------------------------------------------------------------- surrogate MLP
+
+def mlp_nparams():
+    return int(lib().orc_mlp_nparams())
+
+
+def mlp_forward(params, x, bf16=False):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 4)
+    y = np.empty((x.shape[0], 3))
+    lib().orc_mlp_forward(_dp(p), x.shape[0], _dp(x), _dp(y), int(bool(bf16)))
+    return y
+
+
+def mlp_loss_grad(params, x, t, bf16=False):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 4)
+    t = np.ascontiguousarray(t, dtype=np.float64).reshape(-1, 3)
+    g = np.empty(p.shape[0])
+    loss = lib().orc_mlp_loss_grad(_dp(p), x.shape[0], _dp(x), _dp(t), _dp(g), int(bool(bf16)))
+    return float(loss), g
+
+
+def adam_step(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    for a in (p, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_adam_step(_dp(p), _dp(g), _dp(m), _dp(v), p.shape[0], float(lr), float(b1), float(b2), float(eps),
+                        int(t))
+
+
+def bf16_round(v):
+    return float(lib().orc_bf16_round(float(v)))
+
+
+def gelu(v):
+    return float(lib().orc_gelu(float(v)))
