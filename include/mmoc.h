@@ -196,7 +196,19 @@ mmoc_status mmoc_mlp_record(mmoc_ctx* ctx, double t_np1, double dt, const double
 mmoc_status mmoc_mlp_train(mmoc_ctx* ctx, int64_t n_samples, int epochs, int batch, float lr,
                            unsigned long long seed, double* final_loss);
 
-/* Host float32 copies of the master parameters. */
+/* The raw network on caller data: out_dev[n][3] = MLP(in_dev[n][4]) (inputs
+ * already scaled), float32 device arrays. */
+mmoc_status mmoc_mlp_forward(mmoc_ctx* ctx, const float* in_dev, int64_t n, float* out_dev);
+
+/* Loss 1/(3n) sum |MLP(in) - target|^2 and its gradient with respect to the
+ * parameters (grad_dev: float32 device array of mmoc_mlp_nparams() entries),
+ * computed by the training kernels (n a multiple of 64); *loss may be NULL.
+ * Synchronises. */
+mmoc_status mmoc_mlp_loss_grad(mmoc_ctx* ctx, const float* in_dev, const float* target_dev, int64_t n,
+                               float* grad_dev, double* loss);
+
+/* Host float32 copies of the master parameters (set also clears the Adam
+ * moments). */
 mmoc_status mmoc_mlp_get_weights(mmoc_ctx* ctx, float* host_params, int64_t n);
 mmoc_status mmoc_mlp_set_weights(mmoc_ctx* ctx, const float* host_params, int64_t n);
 

@@ -1,0 +1,57 @@
+// mmoc_ctx.h -- the library context and host helpers shared by the
+// library's translation units (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/mmoc.h"
+#include "mmoc_internal.h"
+
+struct mlp_state;
+
+struct mmoc_ctx {
+    int dim = 0, level = 0, n = 0, m = 0;
+    mmoc_precision prec = MMOC_FP64;
+    mmoc_options opt{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+
+    bool mesh_ok = false;
+    int blend = 0;
+    int nm = 0;
+    int64_t npm = 0, nslots = 0, N = 0;
+    mmoc::MacroGeo* geo_d = nullptr;
+    uint64_t* owned_d = nullptr;     // unique order
+    int32_t* slot_uid_d = nullptr;
+    void* va_d[2] = {nullptr, nullptr};  // per level: (u_x,u_y) pairs, or (u_x,u_y,u_z) triples (3D float32)
+    void* vb_d[2] = {nullptr, nullptr};  // per level: u_z (3D float64)
+    void* cs_d = nullptr;                // scalar
+    int swap = 0;                        // array set holding t_n
+    bool vel_set[2] = {false, false};
+    bool scalar_set = false;
+    bool stationary = false;
+    unsigned long long* stats_d = nullptr;
+
+    mlp_state* mlp = nullptr;
+};
+
+
+mmoc_status fail(mmoc_ctx* c, mmoc_status st, const char* fmt, ...);
+mmoc_status hip_fail(mmoc_ctx* c, hipError_t e, const char* what);
+mmoc_status check_dev(mmoc_ctx* c, const void* p, size_t bytes, size_t align, const char* name);
+// validates the arguments of a trace step (fields set, dt, substeps, outputs)
+mmoc_status mmoc_check_step_args(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X);
+// launches the RK4 tracer on the particles order[0..n) (order null: all, lane t
+// traces DoF t); n_dev (optional) is a device-side count that bounds the lanes
+mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* order,
+                              int64_t n, const unsigned long long* n_dev = nullptr);
+void mmoc_mlp_free_state(mmoc_ctx* c);
+
+#define HIPCHK(ctx, call, what)                                \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what);  \
+    } while (0)

@@ -24,38 +24,10 @@
 #include <vector>
 
 #include "../../include/mmoc.h"
+#include "mmoc_ctx.h"
 #include "mmoc_internal.h"
 
 using mmoc::MacroGeo;
-
-struct mmoc_ctx {
-    int dim = 0, level = 0, n = 0, m = 0;
-    mmoc_precision prec = MMOC_FP64;
-    mmoc_options opt{};
-    hipStream_t stream = nullptr;
-    int device = 0;
-    std::string err;
-
-    bool mesh_ok = false;
-    int blend = 0;
-    int nm = 0;
-    int64_t npm = 0, nslots = 0, N = 0;
-    MacroGeo* geo_d = nullptr;
-    uint64_t* owned_d = nullptr;     // unique order
-    int32_t* slot_uid_d = nullptr;
-    void* va_d[2] = {nullptr, nullptr};  // per level: (u_x,u_y) pairs, or (u_x,u_y,u_z) triples (3D float32)
-    void* vb_d[2] = {nullptr, nullptr};  // per level: u_z (3D float64)
-    void* cs_d = nullptr;                // scalar
-    int swap = 0;                        // array set holding t_n
-    bool vel_set[2] = {false, false};
-    bool scalar_set = false;
-    bool stationary = false;
-    unsigned long long* stats_d = nullptr;
-
-    struct mlp_state* mlp = nullptr;
-};
-
-namespace {
 
 mmoc_status fail(mmoc_ctx* c, mmoc_status st, const char* fmt, ...)
 {
@@ -75,11 +47,9 @@ mmoc_status hip_fail(mmoc_ctx* c, hipError_t e, const char* what)
     return fail(c, e == hipErrorOutOfMemory ? MMOC_E_NOMEM : MMOC_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIPCHK(ctx, call, what)                   \
-    do {                                          \
-        hipError_t e_ = (call);                   \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
-    } while (0)
+namespace {
+
+}  // namespace
 
 // A device pointer must be device memory of the context's GPU, aligned, and
 // its allocation must hold `bytes` from p on.
@@ -108,6 +78,8 @@ mmoc_status check_dev(mmoc_ctx* c, const void* p, size_t bytes, size_t align, co
         return fail(c, MMOC_E_ARG, "%s: allocation too small (%zu bytes needed from this address)", name, bytes);
     return MMOC_OK;
 }
+
+namespace {
 
 template <typename T>
 mmoc_status dev_alloc(mmoc_ctx* c, T** p, size_t count, const char* what)
@@ -163,9 +135,6 @@ double invert(int d, const double* B, double* Bi)
 void free_all(mmoc_ctx* c);
 
 }  // namespace
-
-// surrogate state is defined in mmoc_mlp.cpp
-void mmoc_mlp_free_state(mmoc_ctx* c);
 
 extern "C" {
 
@@ -530,12 +499,13 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
 // Shared by the plain and the surrogate step: launches the RK4 tracer on n
 // particles whose unique ids are order[0..n) (all particles: the lane order).
 mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* order,
-                              int64_t n)
+                              int64_t n, const unsigned long long* n_dev)
 {
     auto fill = [&](auto& a) {
         a.geo = c->geo_d;
         a.owned = c->owned_d;
         a.order = order;
+        a.n_dev = n_dev;
         a.n = n;
         a.xstride = c->N;
         a.nm = c->nm;

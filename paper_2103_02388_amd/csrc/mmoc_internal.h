@@ -68,6 +68,7 @@ struct TraceArgs {
     const MacroGeo* geo;
     const uint64_t* owned;   // [n_unique] (macro, I, J, K) per DoF, unique order
     const int32_t* order;    // [n] unique ids in lane order, or null: lane t traces DoF t
+    const unsigned long long* n_dev;  // if set: lanes t >= *n_dev do nothing (device-side count)
     const T* va[2];
     const T* vb[2];
     const T* cs;
@@ -92,6 +93,11 @@ struct TraceArgs {
 // side checks every argument before calling them.
 hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s);
 hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
+// chat = c_h^n(X) for every particle, X given ([dim][n]); the walk starts in
+// the particle's own macro (uses geo, owned, cs, n, nm, npm, level_n,
+// max_hops, eps_in, eps32_*, c_hat, X (read), stats)
+hipError_t launch_scalar_eval_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s);
+hipError_t launch_scalar_eval_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
 hipError_t launch_dof_coords(int dim, int blend, const MacroGeo* geo, const uint64_t* owned,
                              int64_t n, int level_n, double* out, hipStream_t s);
 // Copy of a unique-layout field into block slots: component i of DoF

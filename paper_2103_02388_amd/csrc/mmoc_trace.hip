@@ -31,6 +31,7 @@
 // Workgroups are remapped so that each of the 8 XCDs (own L2 each) receives
 // one contiguous eighth of the particle range.
 #include "mmoc_internal.h"
+#include "mmoc_mlp_internal.h"
 
 #include <math.h>
 
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP
 void trace_fp64_kernel(const TraceArgs<double> A)
 {
     const int64_t t = logical_block() * kTB + threadIdx.x;
-    const bool active = t < A.n;
+    const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
     unsigned flags = 0;
     if (active) {
         const int64_t pid = A.order ? (int64_t)A.order[t] : t;
@@ -708,7 +709,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP
 void trace_fp32_kernel(const TraceArgs<float> A)
 {
     const int64_t t = logical_block() * kTB + threadIdx.x;
-    const bool active = t < A.n;
+    const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
     unsigned flags = 0;
     if (active) {
         const int64_t pid = A.order ? (int64_t)A.order[t] : t;
@@ -769,6 +770,143 @@ void trace_fp32_kernel(const TraceArgs<float> A)
     count_flags(A.stats, active, flags);
 }
 
+// ------------------------------------------------- scalar at given points
+
+// chat_i = c_h^n(X_i) for departure points produced elsewhere (the
+// surrogate): the walk starts in the particle's own macro.
+template <int DIM, int BLEND>
+__global__ __launch_bounds__(kTB) void scalar_eval_fp64_kernel(const TraceArgs<double> A)
+{
+    const int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x;
+    const bool active = t < A.n;
+    unsigned flags = 0;
+    if (active) {
+        int M = (int)(A.owned[t] >> 36);
+        double Y[DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) Y[i] = A.X[(int64_t)i * A.xstride + t];
+        Geo64<DIM, BLEND> G;
+        G.load(A.geo, M);
+        double s[DIM];
+        double l0 = G.ref(Y, s);
+        double lmin = lam_min<DIM, double>(l0, s);
+        if (lmin < -A.eps_in) {
+            const unsigned r =
+                walk64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, Y[0], Y[1], DIM == 3 ? Y[DIM - 1] : 0.0);
+            flags |= r >> 27;
+            M = (int)(r & ((1u << 27) - 1));
+            G.load(A.geo, M);
+            l0 = G.ref(Y, s);
+            lmin = lam_min<DIM, double>(l0, s);
+        }
+        Stencil<DIM, double> st;
+        micro<DIM, double>(s, l0, lmin, A.level_n, st);
+        const double v = gather_scalar<DIM, double, double>(A, (uint32_t)M * (uint32_t)A.npm, st);
+        if (v != v) flags |= LF_NAN;
+        A.c_hat[t] = v;
+    }
+    (void)flags;
+}
+
+template <int DIM, int BLEND>
+__global__ __launch_bounds__(kTB) void scalar_eval_fp32_kernel(const TraceArgs<float> A)
+{
+    const int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x;
+    if (t >= A.n) return;
+    int M = (int)(A.owned[t] >> 36);
+    double Y[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) Y[i] = A.X[(int64_t)i * A.xstride + t];
+    Geo32<DIM, BLEND> G;
+    G.load(A.geo, M);
+    uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
+    Stencil<DIM, float> st;
+    unsigned flags = 0;
+    locate32<DIM, BLEND>(A, M, G, mbase, Y, st, flags);
+    A.c_hat[t] = gather_scalar<DIM, float, float>(A, mbase, st);
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    // splitmix64 finaliser (Steele, Lea, Flood 2014)
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double unit_hash(uint64_t seed, uint64_t i)
+{
+    return (double)(mix64(seed ^ mix64(i)) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// one thread per tile: clear the tile's flags, then select its checked particles
+__global__ __launch_bounds__(256) void select_check_kernel(int64_t n, int tile, uint64_t seed, float fraction,
+                                                           int32_t* ids, unsigned long long* n_ids,
+                                                           unsigned char* checked, unsigned char* tile_flag)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i0 = k * tile;
+    if (i0 >= n) return;
+    const int64_t i1 = i0 + tile < n ? i0 + tile : n;
+    tile_flag[k] = 0;
+    int64_t best = i0;
+    double hb = 2.0;
+    bool any = false;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double h = unit_hash(seed, (uint64_t)i);
+        const bool c = h < (double)fraction;
+        checked[i] = c;
+        if (c) {
+            any = true;
+            ids[atomicAdd(n_ids, 1ull)] = (int32_t)i;
+        }
+        if (h < hb) {
+            hb = h;
+            best = i;
+        }
+    }
+    if (!any) {
+        checked[best] = 1;
+        ids[atomicAdd(n_ids, 1ull)] = (int32_t)best;
+    }
+}
+
+__global__ __launch_bounds__(256) void residual_kernel(int dim, int64_t n, int tile, const int32_t* __restrict__ ids,
+                                                       const unsigned long long* __restrict__ n_ids,
+                                                       const double* __restrict__ Xrk, double* __restrict__ X,
+                                                       double tol, unsigned char* tile_flag, unsigned long long* stats)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if ((unsigned long long)k >= *n_ids) return;
+    const int64_t i = ids[k];
+    double r = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        const double a = X[(int64_t)d * n + i], b = Xrk[(int64_t)d * n + i];
+        const double e = fabs(a - b);
+        r = (e > r || e != e) ? e : r;
+        X[(int64_t)d * n + i] = b;  // a checked particle keeps its RK4 result
+    }
+    if (!(r <= 0.5 * tol)) tile_flag[i / tile] = 1;
+    if (r != r) r = INFINITY;
+    unsigned long long bits;
+    __builtin_memcpy(&bits, &r, sizeof bits);
+    atomicMax(stats + ST_MAXRES_BITS, bits);  // non-negative doubles order like their bits
+    atomicAdd(stats + ST_CHECKED, 1ull);
+}
+
+__global__ __launch_bounds__(256) void fallback_list_kernel(int64_t n, int tile, const unsigned char* tile_flag,
+                                                            const unsigned char* checked, int32_t* ids,
+                                                            unsigned long long* n_ids, unsigned long long* stats)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    if (tile_flag[i / tile] && !checked[i]) {
+        ids[atomicAdd(n_ids, 1ull)] = (int32_t)i;
+        atomicAdd(stats + ST_FALLBACK, 1ull);
+    }
+}
+
 inline unsigned grid_xcd(int64_t n)
 {
     int64_t b = (n + kTB - 1) / kTB;
@@ -797,6 +935,63 @@ hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hip
     }
     return hipGetLastError();
 }
+
+template <typename T, typename K2, typename K3, typename K3b>
+hipError_t launch_plain(int dim, int blend, const T& a, hipStream_t s, K2 k2, K3 k3, K3b k3b)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + kTB - 1) / kTB)), block(kTB);
+    if (dim == 2 && !blend) k2<<<grid, block, 0, s>>>(a);
+    else if (dim == 3 && !blend) k3<<<grid, block, 0, s>>>(a);
+    else if (dim == 3 && blend) k3b<<<grid, block, 0, s>>>(a);
+    else return hipErrorNotSupported;
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_eval_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s)
+{
+    return launch_plain(dim, blend, a, s, scalar_eval_fp64_kernel<2, 0>, scalar_eval_fp64_kernel<3, 0>,
+                        scalar_eval_fp64_kernel<3, 1>);
+}
+
+hipError_t launch_scalar_eval_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
+{
+    return launch_plain(dim, blend, a, s, scalar_eval_fp32_kernel<2, 0>, scalar_eval_fp32_kernel<3, 0>,
+                        scalar_eval_fp32_kernel<3, 1>);
+}
+
+namespace mlp {
+
+hipError_t launch_select_check(int64_t n, int tile, uint64_t seed, float fraction, int32_t* ids,
+                               unsigned long long* n_ids, unsigned char* checked, unsigned char* tile_flag,
+                               hipStream_t s)
+{
+    const int64_t ntiles = (n + tile - 1) / tile;
+    if (ntiles <= 0) return hipSuccess;
+    select_check_kernel<<<(unsigned)((ntiles + 255) / 256), 256, 0, s>>>(n, tile, seed, fraction, ids, n_ids,
+                                                                          checked, tile_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int dim, int64_t n, int tile, const int32_t* ids, const unsigned long long* n_ids,
+                           const double* Xrk, double* X, double tol, unsigned char* tile_flag,
+                           unsigned long long* stats, int64_t max_ids, hipStream_t s)
+{
+    if (max_ids <= 0) return hipSuccess;
+    residual_kernel<<<(unsigned)((max_ids + 255) / 256), 256, 0, s>>>(dim, n, tile, ids, n_ids, Xrk, X, tol,
+                                                                       tile_flag, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback_list(int64_t n, int tile, const unsigned char* tile_flag, const unsigned char* checked,
+                                int32_t* ids, unsigned long long* n_ids, unsigned long long* stats, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    fallback_list_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, tile, tile_flag, checked, ids, n_ids, stats);
+    return hipGetLastError();
+}
+
+}  // namespace mlp
 
 hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
 {

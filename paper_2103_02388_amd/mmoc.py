@@ -32,7 +32,7 @@ EXPORTED = [
     "mmoc_set_scalar", "mmoc_trace_step", "mmoc_get_stats", "mmoc_reset_stats", "mmoc_mlp_nparams",
     "mmoc_mlp_configure", "mmoc_mlp_record", "mmoc_mlp_train", "mmoc_mlp_get_weights",
     "mmoc_mlp_set_weights", "mmoc_mlp_infer", "mmoc_trace_step_surrogate", "mmoc_last_error",
-    "mmoc_destroy",
+    "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad",
 ]
 
 
@@ -90,6 +90,8 @@ def lib():
         "mmoc_mlp_get_weights": (st, [P, P, I64]),
         "mmoc_mlp_set_weights": (st, [P, P, I64]),
         "mmoc_mlp_infer": (st, [P, D, D, P]),
+        "mmoc_mlp_forward": (st, [P, P, I64, P]),
+        "mmoc_mlp_loss_grad": (st, [P, P, P, I64, P, C.POINTER(D)]),
         "mmoc_trace_step_surrogate": (st, [P, D, D, I, C.c_float, D, I64, P, P]),
         "mmoc_last_error": (C.c_char_p, [P]),
         "mmoc_destroy": (None, [P]),
@@ -222,6 +224,17 @@ def mmoc_mlp_set_weights(ctx, w):
     _check(ctx, lib().mmoc_mlp_set_weights(ctx, w.ctypes.data_as(C.c_void_p), w.shape[0]))
 
 
+def mmoc_mlp_forward(ctx, inp: torch.Tensor, out: torch.Tensor):
+    _check(ctx, lib().mmoc_mlp_forward(ctx, _ptr(inp), int(inp.shape[0]), _ptr(out)))
+
+
+def mmoc_mlp_loss_grad(ctx, inp: torch.Tensor, target: torch.Tensor, grad: torch.Tensor):
+    loss = C.c_double()
+    _check(ctx, lib().mmoc_mlp_loss_grad(ctx, _ptr(inp), _ptr(target), int(inp.shape[0]), _ptr(grad),
+                                         C.byref(loss)))
+    return loss.value
+
+
 def mmoc_mlp_infer(ctx, t_np1, dt, X: torch.Tensor):
     _check(ctx, lib().mmoc_mlp_infer(ctx, float(t_np1), float(dt), _ptr(X)))
 
@@ -307,3 +320,34 @@ class Tracer:
 
     def reset_stats(self):
         mmoc_reset_stats(self.ctx)
+
+
+def _tracer_mlp_methods():
+    def mlp_configure(self, lo, hi, U):
+        mmoc_mlp_configure(self.ctx, lo, hi, U)
+
+    def mlp_record(self, t_np1, dt, X, capacity):
+        mmoc_mlp_record(self.ctx, t_np1, dt, X, capacity)
+
+    def mlp_train(self, n_samples, epochs, batch=8192, lr=1e-3, seed=5):
+        return mmoc_mlp_train(self.ctx, n_samples, epochs, batch, lr, seed)
+
+    def mlp_infer(self, t_np1, dt, X=None):
+        if X is None:
+            X = torch.empty((self.dim, self.N), dtype=torch.float64, device=self.device)
+        mmoc_mlp_infer(self.ctx, t_np1, dt, X)
+        return X
+
+    def trace_step_surrogate(self, t_np1, dt, substeps, check_fraction=0.01, tol=1e-4, step=0, c_hat=None, X=None):
+        if c_hat is None:
+            c_hat = torch.empty(self.N, dtype=self.scalar_dtype, device=self.device)
+        if X is None:
+            X = torch.empty((self.dim, self.N), dtype=torch.float64, device=self.device)
+        mmoc_trace_step_surrogate(self.ctx, t_np1, dt, substeps, check_fraction, tol, step, c_hat, X)
+        return c_hat, X
+
+    for f in (mlp_configure, mlp_record, mlp_train, mlp_infer, trace_step_surrogate):
+        setattr(Tracer, f.__name__, f)
+
+
+_tracer_mlp_methods()

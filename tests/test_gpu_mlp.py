@@ -1,0 +1,223 @@
+"""The flow-map surrogate on the GPU.
+
+* forward pass and gradients of the bf16-matrix-core kernels against the CPU
+  reference with the same bf16 rounding points, and against plain float64;
+* training on the tracer's own departure points lowers the loss;
+* the check / fallback policy: poisoned weights send every tile to the RK4
+  fallback (the step then equals the plain tracer), an infinite tolerance
+  keeps the network everywhere except at the checked particles;
+* the gain of a trained surrogate over the tracer on the 3D swirl workload,
+  with the true error of every particle measured against the CPU oracle.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2103_02388_amd import mmoc
+from paper_2103_02388_amd import workloads as W
+
+from gpu_helpers import Pair, field_gpu, rel_c, rel_x
+
+pytestmark = pytest.mark.gpu
+
+
+def init_params(seed):
+    rng = np.random.default_rng(seed)
+    n = mmoc.mmoc_mlp_nparams()
+    p = np.empty(n)
+    off = 0
+    for (o, i) in ((64, 4), (64, 64), (64, 64), (3, 64)):
+        p[off:off + o * i] = rng.normal(size=o * i) * math.sqrt(2.0 / i)
+        off += o * i
+        p[off:off + o] = rng.normal(size=o) * 0.1
+        off += o
+    return p
+
+
+def swirl_tracer(level=2, precision=mmoc.MMOC_FP64):
+    wl = W.swirl3d()
+    tr = mmoc.Tracer.from_workload(wl, level=level, precision=precision)
+    tr.mlp_configure([0, 0, 0, 0], [1, 1, 1, W.SWIRL_T], 2.0)
+    return wl, tr
+
+
+def test_forward_matches_reference():
+    wl, tr = swirl_tracer()
+    p = init_params(1)
+    mmoc.mmoc_mlp_set_weights(tr.ctx, p.astype(np.float32))
+    p32 = p.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-1, 1, size=(1000, 4))
+    xin = torch.tensor(x, dtype=torch.float32, device="cuda")
+    out = torch.empty((1000, 3), dtype=torch.float32, device="cuda")
+    mmoc.mmoc_mlp_forward(tr.ctx, xin, out)
+    torch.cuda.synchronize()
+    y = out.cpu().numpy().astype(np.float64)
+    x32 = xin.cpu().numpy().astype(np.float64)
+    ref16 = O.mlp_forward(p32, x32, bf16=True)
+    ref64 = O.mlp_forward(p32, x32, bf16=False)
+    s = np.abs(ref64).max()
+    e16 = np.abs(y - ref16).max() / s
+    e64 = np.abs(y - ref64).max() / s
+    print("forward: vs bf16 reference %.2e, vs fp64 %.2e" % (e16, e64))
+    assert e16 <= 5e-3 and e64 <= 3e-2
+
+
+def test_gradients_match_reference():
+    wl, tr = swirl_tracer()
+    p = init_params(3)
+    mmoc.mmoc_mlp_set_weights(tr.ctx, p.astype(np.float32))
+    p32 = p.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(4)
+    n = 256
+    x = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
+    t = (rng.normal(size=(n, 3)) * 0.5).astype(np.float32)
+    g = torch.empty(mmoc.mmoc_mlp_nparams(), dtype=torch.float32, device="cuda")
+    loss = mmoc.mmoc_mlp_loss_grad(tr.ctx, torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"), g)
+    g = g.cpu().numpy().astype(np.float64)
+    l16, g16 = O.mlp_loss_grad(p32, x.astype(np.float64), t.astype(np.float64), bf16=True)
+    l64, g64 = O.mlp_loss_grad(p32, x.astype(np.float64), t.astype(np.float64), bf16=False)
+    assert abs(loss - l16) <= 1e-3 * l16
+    # per layer block, relative in the 2-norm
+    blocks = [(0, 256), (256, 320), (320, 4416), (4416, 4480), (4480, 8576), (8576, 8640), (8640, 8832),
+              (8832, 8835)]
+    for a, b in blocks:
+        r16 = np.linalg.norm(g[a:b] - g16[a:b]) / np.linalg.norm(g16[a:b])
+        r64 = np.linalg.norm(g[a:b] - g64[a:b]) / np.linalg.norm(g64[a:b])
+        print("grad block %d:%d rel vs bf16 ref %.2e, vs fp64 %.2e" % (a, b, r16, r64))
+        assert r16 <= 1e-2 and r64 <= 5e-2
+
+
+def record_swirl(tr, wl, steps, dt=None):
+    dt = dt or wl.dt
+    x = tr.dof_coords()
+    xt = x.t().contiguous()
+    cap = steps * tr.N
+    tr.set_scalar(W.two_blobs(xt).contiguous())
+    for n in range(steps):
+        tr.set_velocity(0, W.swirl_velocity(xt, n * dt).t().contiguous())
+        tr.set_velocity(1, W.swirl_velocity(xt, (n + 1) * dt).t().contiguous())
+        _, X = tr.trace_step(dt, 4)
+        tr.mlp_record((n + 1) * dt, dt, X, cap)
+    return x
+
+
+def test_training_lowers_the_loss():
+    wl, tr = swirl_tracer(level=3)
+    record_swirl(tr, wl, 4)
+    l1 = tr.mlp_train(65536, 1, batch=4096, lr=1e-3)
+    l2 = tr.mlp_train(65536, 10, batch=4096, lr=1e-3)
+    print("loss after 1 epoch %.3e, after 10 more %.3e" % (l1, l2))
+    assert l2 < 0.5 * l1
+
+
+def test_poisoned_weights_fall_back_everywhere():
+    wl = W.swirl3d()
+    for prec in (mmoc.MMOC_FP64, mmoc.MMOC_FP32_MIXED):
+        p = Pair(wl, level=3, precision=prec)
+        p.tr.mlp_configure([0, 0, 0, 0], [1, 1, 1, W.SWIRL_T], 2.0)
+        bad = init_params(7)
+        bad[-3:] = 50.0  # output bias: departure points far off
+        mmoc.mmoc_mlp_set_weights(p.tr.ctx, bad.astype(np.float32))
+        t_n = 0.3
+        p.set_fields(t_n, wl.dt, False)
+        p.tr.reset_stats()
+        ch_s, X_s = p.tr.trace_step_surrogate(t_n + wl.dt, wl.dt, 4, 0.01, 1e-4, step=3)
+        st = p.tr.stats()
+        ch, X = p.tr.trace_step(wl.dt, 4)
+        torch.cuda.synchronize()
+        assert st["n_checked"] + st["n_fallback"] == p.tr.N
+        assert np.array_equal(X_s.cpu().numpy(), X.cpu().numpy())
+        assert rel_c(ch_s.double().cpu().numpy(), ch.double().cpu().numpy()) <= (1e-14 if prec == 0 else 1e-6)
+
+
+def test_infinite_tolerance_keeps_the_network():
+    wl, tr = swirl_tracer(level=3)
+    p = init_params(8)
+    mmoc.mmoc_mlp_set_weights(tr.ctx, p.astype(np.float32))
+    x = tr.dof_coords()
+    xt = x.t().contiguous()
+    tr.set_velocity(0, W.swirl_velocity(xt, 0.3).t().contiguous())
+    tr.set_velocity(1, W.swirl_velocity(xt, 0.3 + wl.dt).t().contiguous())
+    tr.set_scalar(W.two_blobs(xt).contiguous())
+    tr.reset_stats()
+    ch, X = tr.trace_step_surrogate(0.3 + wl.dt, wl.dt, 4, 0.05, float("inf"), step=1)
+    st = tr.stats()
+    Xn = tr.mlp_infer(0.3 + wl.dt, wl.dt)
+    _, Xr = tr.trace_step(wl.dt, 4)
+    torch.cuda.synchronize()
+    X, Xn, Xr = X.cpu().numpy(), Xn.cpu().numpy(), Xr.cpu().numpy()
+    assert st["n_fallback"] == 0 and 0 < st["n_checked"] < tr.N
+    same_net = np.all(X == Xn, axis=0)
+    same_rk = np.all(X == Xr, axis=0)
+    assert np.all(same_net | same_rk)
+    assert same_rk.sum() >= st["n_checked"]
+
+
+def test_surrogate_gain_on_swirl():
+    """Train on steps 1-10 (2e6 sampled pairs, 30 epochs), then run step 11
+    with the surrogate at several tolerances: report the fallback fraction,
+    the time per step against the plain tracers, and the true error of a
+    seeded sample of particles against the CPU oracle.  At every tolerance
+    the error must stay within it (the check sample and the tile fallback
+    are what guarantee that); the speed-up is reported, not asserted."""
+    wl = W.swirl3d()
+    p = Pair(wl, precision=mmoc.MMOC_FP32_MIXED)
+    tr = p.tr
+    tr.mlp_configure([0, 0, 0, 0], [1, 1, 1, W.SWIRL_T], 2.0)
+    xt = p.xg.t().contiguous()
+    U = torch.stack([W.swirl_velocity(xt, n * wl.dt).t().contiguous() for n in range(12)])
+    c0 = W.two_blobs(xt).contiguous()
+    tr.set_scalar(c0)
+    cap = 10 * tr.N
+    for n in range(10):
+        tr.set_velocity(0, U[n])
+        tr.set_velocity(1, U[n + 1])
+        _, X = tr.trace_step(wl.dt, 4)
+        tr.mlp_record((n + 1) * wl.dt, wl.dt, X, cap)
+    t0 = time.perf_counter()
+    loss = tr.mlp_train(2_000_000, 30, batch=8192, lr=1e-3, seed=5)
+    t_train = time.perf_counter() - t0
+    n = 10
+    tr.set_velocity(0, U[n])
+    tr.set_velocity(1, U[n + 1])
+    xc = torch.from_numpy(p.xc.T.copy())
+    p.u0c = np.ascontiguousarray(W.swirl_velocity(xc, n * wl.dt).numpy().T)
+    p.u1c = np.ascontiguousarray(W.swirl_velocity(xc, (n + 1) * wl.dt).numpy().T)
+    p.cc = W.two_blobs(xc).numpy()
+    ids = np.sort(np.random.default_rng(n).choice(tr.N, 4000, replace=False))
+    _, Xr, _ = p.oracle_step(wl.dt, 4, ids=ids, threads=8)
+
+    def timeit(f, k=10):
+        f()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(k):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / k
+
+    t_rk = timeit(lambda: tr.trace_step(wl.dt, 4))
+    Xnet = tr.mlp_infer((n + 1) * wl.dt, wl.dt)
+    torch.cuda.synchronize()
+    net_err = np.abs(Xnet.cpu().numpy()[:, ids] - Xr).max()
+    t_inf = timeit(lambda: tr.mlp_infer((n + 1) * wl.dt, wl.dt, Xnet))
+    rows = []
+    for tol in (1e-4, 1e-3, 1e-2, 3e-2):
+        tr.reset_stats()
+        ch, X = tr.trace_step_surrogate((n + 1) * wl.dt, wl.dt, 4, 0.01, tol, step=n)
+        st = tr.stats()
+        err = np.abs(X.cpu().numpy()[:, ids] - Xr).max()
+        t_s = timeit(lambda: tr.trace_step_surrogate((n + 1) * wl.dt, wl.dt, 4, 0.01, tol, step=n))
+        rows.append((tol, (st["n_fallback"] + st["n_checked"]) / tr.N, err, t_s))
+        assert err <= tol
+    print("surrogate: train %.2fs, loss %.3e, network-only max error %.2e, inference %.1f us, fp32 rk4 %.1f us"
+          % (t_train, loss, net_err, t_inf * 1e6, t_rk * 1e6))
+    for tol, fb, err, t_s in rows:
+        print("surrogate tol %.0e: rk4 fraction %.3f, max true error %.2e, step %.1f us, speed-up vs fp32 rk4 %.2fx"
+              % (tol, fb, err, t_s * 1e6, t_rk / t_s))
+    assert loss < 1e-3
