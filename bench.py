@@ -1,29 +1,32 @@
 #!/usr/bin/env python3
 """Throughput of the MMOC particle tracer on one MI355X.
 
-Workload (default): the 3D swirl -- unit cube of 6 Kuhn macro tetrahedra
-refined to level 5, 65^3 = 274625 P2 DoFs = particles, LeVeque's deformation
-field with g(t) = cos(pi t / 1.5) sampled at every time level, two Gaussian
-blobs as the scalar, dt = T/20 (CFL ~ 5), 4 RK4 sub-steps, 50 time steps.
+Workload: the 3D swirl -- unit cube of 6 Kuhn macro tetrahedra refined to
+level 5, 65^3 = 274625 P2 DoFs = particles, LeVeque's deformation field with
+g(t) = cos(pi t / 1.5) sampled at every time level, two Gaussian blobs as the
+scalar, dt = T/20 (CFL ~ 5), 4 RK4 sub-steps, a 50-step run.
 
 One timed step is one full MMOC advection step of the time loop: the new
 velocity level and the current scalar are copied into the library's block
 layout (field ingestion), then every particle is created, traced back with
 RK4 and the scalar evaluated at its departure point; the result is the next
 step's scalar.  All inputs (every velocity level of the run) are resident in
-device memory before timing starts.  value = particles traced per second.
+device memory before timing starts.  value = particles per second of the
+float64 tracer (error <= 1e-12 against the CPU oracle); the float32-mixed
+tracer (<= 1e-5) and the surrogate step (network + RK4 check + fallback,
+<= 1e-4) are measured on the same run and reported beside it.
 
-Printed: one JSON line.  The dominant kernel's roofline entry uses its
-algorithmic flops per particle (FMA = 2, listed in the design notes) and the
-kernel's mean duration from HIP events recorded around each launch inside the
-timed loop.  cpu_baseline runs the CPU oracle (single-threaded FP64 C) on a
+The roofline entry is for the dominant kernel (the float64 trace): its
+algorithmic flops per particle (FMA = 2, see flops_per_particle) over its
+mean duration from HIP events recorded around each launch on the stream it
+runs on.  cpu_baseline times the CPU oracle (single-threaded float64 C) on a
 bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -33,11 +36,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic flops per particle of one step (FMA counted as 2), per path:
-# per stage evaluation 25 (reference coordinates) + 44 (micro location and
-# P2 basis) + 20 per component and level (P2 sums) + 9 (time lerp, 2 levels)
-# + 12 (stage update); per sub-step 6 more; the scalar evaluation 89.
+TRACE_SRC = os.path.join(ROOT, "paper_2103_02388_amd", "csrc", "mmoc_trace.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "trace_fp64_swirl3d_traffic.json")
+
+
 def flops_per_particle(dim, nlev, S):
+    """Algorithmic flops of one particle's step (FMA = 2).  Per stage
+    evaluation: reference coordinates (offset dim, matrix 2 dim^2, lambda_0
+    dim + 1), micro location and P2 basis (Kuhn sums 2(dim - 1), scaling 2 dim,
+    fractional parts 2 dim, micro barycentrics dim + 1, vertex shape functions
+    3 (dim + 1), edge shape functions 2 per edge), the P2 sums (2 per node,
+    component and level), the time interpolation (3 dim) and the stage update
+    (4 dim); 2 dim per sub-step for the departure point; the scalar evaluation
+    at the end.  The first stage evaluation (at the particle's own DoF) is
+    counted as a full one."""
     nn = (dim + 1) * (dim + 2) // 2
     ref = dim + 2 * dim * dim + dim + 1
     micro = (2 * (dim - 1) + 2 * dim + 2 * dim) + (dim + 1) + 3 * (dim + 1) + 2 * (nn - dim - 1)
@@ -48,15 +60,28 @@ def flops_per_particle(dim, nlev, S):
     return S * (4 * per_eval + 2 * dim) + scalar
 
 
-# compulsory HBM bytes per particle: every unique field value read once,
-# every output written once
 def bytes_per_particle(dim, nlev, real_bytes):
+    """Compulsory HBM bytes of one particle's step: every unique field value
+    read once (velocity levels, scalar), every output written once (chat in
+    the path's real type, X in float64)."""
     return dim * nlev * real_bytes + real_bytes + real_bytes + dim * 8
 
 
 PEAK_FP64_VALU = 78.6e12
-PEAK_FP32_VALU = 78.6e12  # packed FP32 is not used (157.3 TFLOP/s only with packed math)
 PEAK_HBM = 8.0e12
+
+
+def traffic_entry():
+    """HBM bytes per launch of the float64 trace kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    try:
+        d = json.load(open(TRAFFIC))
+        sha = hashlib.sha256(open(TRACE_SRC, "rb").read()).hexdigest()
+        if d.get("source_sha256") != sha:
+            return None
+        return d["hbm_bytes_per_launch"]
+    except Exception:
+        return None
 
 
 def main():
@@ -64,10 +89,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--substeps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="particles in the oracle sample (0: auto)")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--paths", default="fp64,fp32", help="tracer paths to time (fp64 is the headline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (10 times), to scale HBM counters")
     args = ap.parse_args()
@@ -81,20 +106,73 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 10}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(particles are independent; see the sharding notes in DESIGN.md). Use --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (particles are independent; "
+              "the sharding plan is in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    import torch
+    from paper_2103_02388_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.swirl3d()
+    S = args.substeps
+    results = {}
+    paths = args.paths.split(",")
+    if "fp64" not in paths:
+        paths = ["fp64"] + paths
+    for path in paths:
+        results[path] = time_path(wl, path, S, args.steps, args.warmup)
+    N = results["fp64"]["N"]
+    r = results["fp64"]
+    fpp = flops_per_particle(3, 2, S)
+    bpp64 = bytes_per_particle(3, 2, 8)
+    achieved = fpp * N / (r["kernel_ms"] * 1e-3)
+    out = {
+        "metric": "particles traced/sec (RK4+locate+P2 interp) at stated error; FP32/MLP vs FP64",
+        "value": r["value"],
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "swirl3d: unit cube, 6 Kuhn macro tets, level 5, 274625 P2 particles, LeVeque swirl "
+                               "T=1.5, dt=T/20 (CFL~5), RK4 with %d sub-steps, 50-step run" % S,
+                   "particles": N, "substeps": S, "precision": "fp64", "error_bound_vs_oracle": 1e-12},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU,
+                     "traffic": traffic_entry(),
+                     "kernel": "trace_fp64_kernel<3,2,0>", "kernel_ms": r["kernel_ms"], "flop_per_particle": fpp,
+                     "hbm_GBps_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / 1e9,
+                     "hbm_frac_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / PEAK_HBM},
+        "trace_only_particles_per_s": N / (r["kernel_ms"] * 1e-3),
+        "stats": r["stats"],
+    }
+    if "fp32" in results:
+        f = results["fp32"]
+        out["fp32_mixed"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "kernel_ms": f["kernel_ms"],
+                             "trace_only_particles_per_s": N / (f["kernel_ms"] * 1e-3),
+                             "speedup_vs_fp64_step": f["value"] / r["value"],
+                             "speedup_vs_fp64_trace": r["kernel_ms"] / f["kernel_ms"],
+                             "error_bound_vs_oracle": 1e-5,
+                             "tieband_fraction": f["stats"]["n_tieband"] / max(1, f["stats"]["n_particles"])}
+    if not args.no_surrogate:
+        out["surrogate"] = time_surrogate(wl, S, min(args.steps, 50), min(args.warmup, 5), results)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, S)
+    print(json.dumps(out), flush=True)
+
+
+def time_path(wl, path, S, steps, warmup):
     import torch
     from paper_2103_02388_amd import mmoc
     from paper_2103_02388_amd import workloads as W
 
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    wl = W.swirl3d()
-    prec = mmoc.MMOC_FP64 if args.precision == "fp64" else mmoc.MMOC_FP32_MIXED
-    S = args.substeps
+    prec = mmoc.MMOC_FP64 if path == "fp64" else mmoc.MMOC_FP32_MIXED
     tr = mmoc.Tracer.from_workload(wl, precision=prec)
     N = tr.N
     x = tr.dof_coords()
@@ -102,15 +180,11 @@ def main():
     nsteps = wl.steps
     U = torch.stack([W.swirl_velocity(xt, n * wl.dt).t().contiguous() for n in range(nsteps + 1)])
     c0 = W.two_blobs(xt).contiguous()
-    torch.cuda.synchronize()
-
     cur = c0.clone()
-    nxt = torch.empty(N, dtype=torch.float64, device=dev)
-    chat = torch.empty(N, dtype=tr.scalar_dtype, device=dev)
-    X = torch.empty((3, N), dtype=torch.float64, device=dev)
+    chat = torch.empty(N, dtype=tr.scalar_dtype, device="cuda")
+    X = torch.empty((3, N), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     state = {"n": 0}
-    tr.set_velocity(0, U[0])
-    tr.set_velocity(1, U[1])
 
     def step(ev=None):
         n = state["n"] % nsteps
@@ -127,75 +201,93 @@ def main():
         mmoc.mmoc_trace_step(tr.ctx, wl.dt, S, chat, X)
         if ev is not None:
             ev[1].record()
-        if chat.dtype == torch.float64:
-            cur.copy_(chat)
-        else:
-            cur.copy_(chat.double())
+        cur.copy_(chat)  # the next step's scalar (float32 results widened to float64)
         state["n"] += 1
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     tr.reset_stats()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
-    for k in range(args.steps):
+    for k in range(steps):
         step(evs[k])
     e1.record()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall_ms = (t1 - t0) * 1e3
-    gpu_ms = e0.elapsed_time(e1)
-    ms_per_step = max(wall_ms, gpu_ms) / args.steps
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ms = max(wall_ms, e0.elapsed_time(e1)) / steps
+    kern = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    st = {k: (int(v) if isinstance(v, (int, np.integer)) else float(v)) for k, v in tr.stats().items()}
+    tr.close()
+    return {"N": N, "value": N / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": kern, "stats": st}
+
+
+def time_surrogate(wl, S, steps, warmup, results):
+    """Steps 1-10 of the run traced by float64 RK4 and recorded, 2e6 pairs
+    sampled, 30 epochs of training; then steps 11-20 (cycled) with the
+    surrogate (1% check sample, tolerance 1e-4, float32-mixed RK4 fallback)."""
+    import torch
+    from paper_2103_02388_amd import mmoc
+    from paper_2103_02388_amd import workloads as W
+
+    tr = mmoc.Tracer.from_workload(wl, precision=mmoc.MMOC_FP32_MIXED)
+    N = tr.N
+    tr.mlp_configure([0, 0, 0, 0], [1, 1, 1, W.SWIRL_T], 2.0)
+    x = tr.dof_coords()
+    xt = x.t().contiguous()
+    U = torch.stack([W.swirl_velocity(xt, n * wl.dt).t().contiguous() for n in range(21)])
+    c0 = W.two_blobs(xt).contiguous()
+    tr.set_scalar(c0)
+    for n in range(10):
+        tr.set_velocity(0, U[n])
+        tr.set_velocity(1, U[n + 1])
+        _, X = tr.trace_step(wl.dt, S)
+        tr.mlp_record((n + 1) * wl.dt, wl.dt, X, 10 * N)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = tr.mlp_train(2_000_000, 30, batch=8192, lr=1e-3, seed=5)
+    t_train = time.perf_counter() - t0
+    chat = torch.empty(N, dtype=torch.float32, device="cuda")
+    X = torch.empty((3, N), dtype=torch.float64, device="cuda")
+    cur = c0.clone()
+
+    def step(k):
+        n = 10 + k % 10
+        tr.set_velocity(0, U[n])
+        tr.set_velocity(1, U[n + 1])
+        tr.set_scalar(cur)
+        mmoc.mmoc_trace_step_surrogate(tr.ctx, (n + 1) * wl.dt, wl.dt, S, 0.01, 1e-4, n, chat, X)
+        cur.copy_(chat)
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    tr.reset_stats()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
     st = tr.stats()
-
-    nlev = 2
-    fpp = flops_per_particle(3, nlev, S)
-    rb = 8 if prec == mmoc.MMOC_FP64 else 4
-    bpp = bytes_per_particle(3, nlev, rb)
-    achieved = fpp * N / (kern_ms * 1e-3)
-    peak = PEAK_FP64_VALU if prec == mmoc.MMOC_FP64 else PEAK_FP32_VALU
-    value = N / (ms_per_step * 1e-3)
-
-    out = {
-        "metric": "particles traced/sec (RK4+locate+P2 interp) at stated error; FP32/MLP vs FP64",
-        "value": value,
-        "unit": "particles/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == mmoc.MMOC_FP64 else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "swirl3d: unit cube, 6 Kuhn macro tets, level 5, 274625 P2 particles, "
-                               "LeVeque swirl T=1.5, dt=T/20 (CFL~5), RK4 with %d sub-steps, 50-step run" % S,
-                   "particles": N, "substeps": S, "precision": args.precision,
-                   "error_bound_vs_fp64_oracle": 1e-12 if prec == mmoc.MMOC_FP64 else 1e-5},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "trace_%s_kernel<3,2,0>" % ("fp64" if prec == mmoc.MMOC_FP64 else "fp32"),
-                     "kernel_ms": kern_ms, "flop_per_particle": fpp,
-                     "hbm_GBps_algorithmic": bpp * N / (kern_ms * 1e-3) / 1e9,
-                     "hbm_frac_algorithmic": bpp * N / (kern_ms * 1e-3) / PEAK_HBM},
-        "trace_only_particles_per_s": N / (kern_ms * 1e-3),
-        "stats": {k: (int(v) if isinstance(v, (int, np.integer)) else float(v)) for k, v in st.items()},
-    }
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, S, args.cpu_sample)
-    print(json.dumps(out), flush=True)
+    tr.close()
+    fb = (st["n_checked"] + st["n_fallback"]) / (N * steps)
+    out = {"value": N / (ms * 1e-3), "ms_per_step": ms, "train_seconds": t_train, "final_loss": loss,
+           "rk4_fraction": fb, "max_check_residual": st["max_check_residual"], "tolerance": 1e-4,
+           "note": "steps 11-20 (cycled) of the swirl run; the network is trained on steps 1-10"}
+    if "fp64" in results:
+        out["speedup_vs_fp64_step"] = out["value"] / results["fp64"]["value"]
+    if "fp32" in results:
+        out["speedup_vs_fp32_step"] = out["value"] / results["fp32"]["value"]
+    return out
 
 
-def cpu_baseline(wl, S, sample):
-    """The CPU oracle (unchanged, single-threaded) on a seeded sample of the
-    same step's particles, with its own copy of the same inputs."""
+def cpu_baseline(wl, S):
+    """The CPU oracle (unchanged, single-threaded) on the same step's
+    particles with its own copy of the same inputs: full steps repeated until
+    about 10 s of single-core work."""
     import torch
     from oracle import oracle as O
     from paper_2103_02388_amd import workloads as W
@@ -206,25 +298,20 @@ def cpu_baseline(wl, S, sample):
     u0 = np.ascontiguousarray(W.swirl_velocity(xt, 7 * wl.dt).numpy().T)
     u1 = np.ascontiguousarray(W.swirl_velocity(xt, 8 * wl.dt).numpy().T)
     c = W.two_blobs(xt).numpy()
-    # full steps (every particle) repeated until about 10 s of single-core work
-    n = sample or om.N
-    ids = None if n >= om.N else np.sort(np.random.default_rng(0).choice(om.N, n, replace=False))
     reps, total = 0, 0.0
     while reps == 0 or (total < 10.0 and reps < 40):
         t0 = time.perf_counter()
-        om.trace(u0, u1, c, wl.dt, S, ids=ids, threads=1)
+        om.trace(u0, u1, c, wl.dt, S, threads=1)
         total += time.perf_counter() - t0
         reps += 1
-    dt = total
-    n_total = n * reps
     try:
         cpu = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
     except Exception:
         cpu = "unknown"
-    return {"value": n_total / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": "%d x %d particles: full swirl3d step 7 -> 8 repeated, RK4 %d sub-steps, FP64, "
-                      "single thread; host CPU: %s (%d logical cores)" % (reps, n, S, cpu, os.cpu_count() or 0),
-            "seconds": dt}
+    return {"value": om.N * reps / total, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": "%d x %d particles: the full swirl3d step 7 -> 8 repeated, RK4 %d sub-steps, float64, "
+                      "single thread; host CPU: %s (%d logical cores)" % (reps, om.N, S, cpu, os.cpu_count() or 0),
+            "seconds": total}
 
 
 if __name__ == "__main__":
