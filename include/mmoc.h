@@ -166,6 +166,39 @@ mmoc_status mmoc_trace_step(mmoc_ctx* ctx, double dt, int substeps, void* c_hat_
 mmoc_status mmoc_get_stats(mmoc_ctx* ctx, mmoc_stats* out);
 mmoc_status mmoc_reset_stats(mmoc_ctx* ctx);
 
+/* ---------------- benchmark measures and look-back (Sec. 2.3.3, 3.1) ------ */
+
+/* Discrete H0 inner product with the P2 mass matrix M of the refined mesh
+ * (the matrix of the H0 error norm and of the mass m(t) = 1^T M c, Sec. 3.1):
+ * *out = (a - a_sub)^T M (b - b_sub).  All arrays are unique-layout
+ * [n_unique] float64 device arrays; a = NULL stands for the vector of ones,
+ * a_sub / b_sub = NULL for zero.  Exact for P2 functions on affine elements;
+ * a blended mesh returns MMOC_E_UNSUPPORTED.  Deterministic (fixed summation
+ * order); synchronises the stream. */
+mmoc_status mmoc_mass_inner(mmoc_ctx* ctx, const double* a_dev, const double* a_sub_dev, const double* b_dev,
+                            const double* b_sub_dev, double* out);
+
+/* Smallest and largest nodal value of a unique-layout [n_unique] float64
+ * device array (var = max - min and the peak ratio of Sec. 3.1); NaNs are
+ * skipped.  Synchronises the stream. */
+mmoc_status mmoc_field_range(mmoc_ctx* ctx, const double* c_dev, double* min_out, double* max_out);
+
+/* n_steps MMOC steps of length tau with look-back distance b (Sec. 2.3.3),
+ * for a stationary velocity (mmoc_set_stationary(ctx, 1) and level 0 set)
+ * and a float64 context.  Step n (1..n_steps) computes
+ *   c^n = c^{n-b'}(X),  b' = min(b, n),
+ * with X traced back over b' tau in b' * substeps RK4 sub-steps (substeps
+ * per time step; 1 is one RK4 step per tau).  b <= 0 stands for b = infinity:
+ * c^{n_steps} = c^0 at the point traced back over the whole interval, one
+ * trace.  ring_dev: caller-owned float64 device array [ring_len][n_unique];
+ * slot 0 holds c^0 on entry, c^j is kept in slot j % ring_len, and ring_len
+ * must be at least min(b, n_steps) + 1 (1 for b = infinity).  c_out_dev
+ * ([n_unique] float64, must not overlap other ring slots) receives
+ * c^{n_steps}.  The scalar set on ctx is overwritten.  Asynchronous on the
+ * context's stream. */
+mmoc_status mmoc_lookback_run(mmoc_ctx* ctx, double tau, int substeps, int64_t n_steps, int64_t b,
+                              double* ring_dev, int64_t ring_len, double* c_out_dev);
+
 /* ---------------- learned flow-map surrogate (not part of the paper) -------
  * An MLP (x, t_{n+1}) -> scaled displacement, 4 -> 64 -> 64 -> 64 -> 3 with
  * tanh-form GELU (Hendrycks & Gimpel 2016), bf16 weights and activations,
@@ -219,9 +252,9 @@ mmoc_status mmoc_mlp_infer(mmoc_ctx* ctx, double t_np1, double dt, double* X_dev
 /* Surrogate step: inference for all particles, then an RK4 re-trace (FP32
  * mixed tracer, same fields) of a seeded sample of about check_fraction of
  * the particles (hash(seed, step, i) < check_fraction, with at least one per
- * tile of 128 particles); a checked particle with residual
- * |Xhat - X_rk4|_inf > tol takes its RK4 result, and every particle of a tile
- * in which some checked residual exceeds tol/2 is re-traced by RK4 (fallback).
+ * tile of 128 particles); every checked particle keeps its RK4 result, and
+ * every particle of a tile in which some checked residual
+ * |Xhat - X_rk4|_inf exceeds tol/2 is re-traced by RK4 (fallback).
  * Then chat = c_h^n(X) as in mmoc_trace_step.  c_hat_dev: double* for
  * MMOC_FP64 contexts, float* for MMOC_FP32_MIXED.  step seeds the sample. */
 mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* ctx, double t_np1, double dt, int substeps,

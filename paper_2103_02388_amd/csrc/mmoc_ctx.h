@@ -34,6 +34,8 @@ struct mmoc_ctx {
     bool scalar_set = false;
     bool stationary = false;
     unsigned long long* stats_d = nullptr;
+    double* red_d = nullptr;  // partial sums of the metric reductions, red_cap doubles
+    int64_t red_cap = 0;
 
     mlp_state* mlp = nullptr;
 };

@@ -627,6 +627,9 @@ void free_all(mmoc_ctx* c)
     }
     (void)hipFree(c->cs_d);
     (void)hipFree(c->stats_d);
+    (void)hipFree(c->red_d);
+    c->red_d = nullptr;
+    c->red_cap = 0;
     c->geo_d = nullptr;
     c->owned_d = nullptr;
     c->slot_uid_d = nullptr;

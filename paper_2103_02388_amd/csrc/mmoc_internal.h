@@ -110,4 +110,19 @@ struct ScatterDst {
 hipError_t launch_scatter(int ncomp, const int32_t* slot_uid, int64_t nslots, const double* u, int64_t n_unique,
                           const ScatterDst& d, int fp32, hipStream_t s);
 
+// P2 mass matrix of a simplex of unit volume, nodes ordered as vertices
+// 0..d then edges (a, b), a < b, lexicographic; entry (i, j) at m[i * NN + j]
+struct MassRef {
+    double m[100];
+};
+// blocks (partial sums) of one a^T M b launch
+int64_t mass_inner_blocks(int dim, int nm, int n);
+// out[0] = (a - a_sub)^T M (b - b_sub) over the whole refined mesh (a null:
+// ones; a_sub, b_sub null: zero); partial holds mass_inner_blocks doubles
+hipError_t launch_mass_inner(int dim, const MacroGeo* geo, const int32_t* slot_uid, int64_t npm, int nm, int n,
+                             const MassRef& R, const double* a, const double* a_sub, const double* b,
+                             const double* b_sub, double* partial, double* out, hipStream_t s);
+// out[0] = min c, out[1] = max c (NaNs skipped); partial holds 2 nblocks doubles
+hipError_t launch_range(const double* c, int64_t n, double* partial, int64_t nblocks, double* out, hipStream_t s);
+
 }  // namespace mmoc

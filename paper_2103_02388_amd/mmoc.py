@@ -32,7 +32,8 @@ EXPORTED = [
     "mmoc_set_scalar", "mmoc_trace_step", "mmoc_get_stats", "mmoc_reset_stats", "mmoc_mlp_nparams",
     "mmoc_mlp_configure", "mmoc_mlp_record", "mmoc_mlp_train", "mmoc_mlp_get_weights",
     "mmoc_mlp_set_weights", "mmoc_mlp_infer", "mmoc_trace_step_surrogate", "mmoc_last_error",
-    "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad",
+    "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad", "mmoc_mass_inner", "mmoc_field_range",
+    "mmoc_lookback_run",
 ]
 
 
@@ -93,6 +94,9 @@ def lib():
         "mmoc_mlp_forward": (st, [P, P, I64, P]),
         "mmoc_mlp_loss_grad": (st, [P, P, P, I64, P, C.POINTER(D)]),
         "mmoc_trace_step_surrogate": (st, [P, D, D, I, C.c_float, D, I64, P, P]),
+        "mmoc_mass_inner": (st, [P, P, P, P, P, C.POINTER(D)]),
+        "mmoc_field_range": (st, [P, P, C.POINTER(D), C.POINTER(D)]),
+        "mmoc_lookback_run": (st, [P, D, I, I64, I64, P, I64, P]),
         "mmoc_last_error": (C.c_char_p, [P]),
         "mmoc_destroy": (None, [P]),
     }
@@ -245,6 +249,23 @@ def mmoc_trace_step_surrogate(ctx, t_np1, dt, substeps, check_fraction, tol, ste
                                                 _ptr(X)))
 
 
+def mmoc_mass_inner(ctx, a, a_sub, b, b_sub):
+    out = C.c_double()
+    _check(ctx, lib().mmoc_mass_inner(ctx, _ptr(a), _ptr(a_sub), _ptr(b), _ptr(b_sub), C.byref(out)))
+    return out.value
+
+
+def mmoc_field_range(ctx, c):
+    lo, hi = C.c_double(), C.c_double()
+    _check(ctx, lib().mmoc_field_range(ctx, _ptr(c), C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
+
+
+def mmoc_lookback_run(ctx, tau, substeps, n_steps, b, ring: torch.Tensor, c_out: torch.Tensor):
+    _check(ctx, lib().mmoc_lookback_run(ctx, float(tau), int(substeps), int(n_steps), int(b), _ptr(ring),
+                                        int(ring.shape[0]), _ptr(c_out)))
+
+
 def mmoc_last_error(ctx):
     return lib().mmoc_last_error(ctx).decode()
 
@@ -320,6 +341,23 @@ class Tracer:
 
     def reset_stats(self):
         mmoc_reset_stats(self.ctx)
+
+    def mass_inner(self, a=None, a_sub=None, b=None, b_sub=None):
+        """(a - a_sub)^T M (b - b_sub) with the P2 mass matrix (None: ones / zero)."""
+        return mmoc_mass_inner(self.ctx, a, a_sub, b, b_sub)
+
+    def field_range(self, c):
+        return mmoc_field_range(self.ctx, c)
+
+    def lookback_run(self, c0, tau, n_steps, b, substeps=1):
+        """c^{n_steps} from c^0 with look-back distance b (b <= 0: infinity);
+        the velocity must be stationary.  Returns the new field."""
+        span = n_steps if b <= 0 else min(b, n_steps)
+        ring = torch.empty((1 if b <= 0 else span + 1, self.N), dtype=torch.float64, device=self.device)
+        ring[0].copy_(c0)
+        out = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        mmoc_lookback_run(self.ctx, tau, substeps, n_steps, b, ring, out)
+        return out
 
 
 def _tracer_mlp_methods():

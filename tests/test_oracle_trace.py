@@ -160,3 +160,48 @@ def test_mass_matrix_closed_forms(oracle_mod):
         # integral of x_0^2 over the unit square / cube = 1/3; of x_0 x_1 = 1/4
         assert abs(m.mass_quadform(one, x[0] ** 2) - 1 / 3) < 1e-13
         assert abs(m.mass_quadform(x[0], x[1]) - 1 / 4) < 1e-13
+
+
+@pytest.mark.parametrize("steps,b", [(62, 1), (62, 10), (628, 1)])
+def test_paper_table2_finite_lookback(oracle_mod, steps, b):
+    """Table 2 rows with a finite look-back distance (Sec. 2.3.3): every step
+    re-interpolates, so the error is the accumulated interpolation error the
+    paper attributes to the Eulerian-Lagrangian transfer.  The oracle runs the
+    look-back recursion c^n = c^{n-b'}(X_{b'}) step by step; H0 and var must
+    match the printed three digits within 5% and 2e-4."""
+    rows = json.load(open(os.path.join(GOLD, "table2_lookback.json")))["rows"]
+    gold = [r for r in rows if r["steps"] == steps and r["b"] == b][0]
+    wl, m, x = setup(oracle_mod, W.rotation2d, 6)
+    xt = torch.from_numpy(x.T.copy())
+    U = W.rotation_velocity(xt).numpy().T.copy()
+    c0 = W.hill(xt).numpy()
+    tau = 2 * np.pi / steps
+    hist = {0: c0}
+    for n in range(1, steps + 1):
+        bp = min(b, n)
+        hist[n], _, _ = m.trace(U, None, hist[n - bp], bp * tau, bp, threads=4)
+        hist.pop(n - b - 1, None)
+    c = hist[steps]
+    e = c0 - c
+    h0 = np.sqrt(m.mass_quadform(e, e))
+    assert abs(h0 / gold["H0"] - 1) < 0.05, h0
+    assert abs((c.max() - c.min()) - gold["var"]) < 2e-4
+
+
+def test_paper_table1_b_infinity(oracle_mod):
+    """Table 1, P2, b = infinity (three bodies, one revolution in 6283
+    steps): tracing the whole revolution back in one go returns every
+    particle to its own position up to the RK4 error of the exact rotation,
+    so the error and the mass change are at rounding level and var is 1."""
+    gold = [r for r in json.load(open(os.path.join(GOLD, "table1_p2.json")))["rows"] if r["b"] == 0][0]
+    wl, m, x = setup(oracle_mod, W.rotation2d, 6)
+    xt = torch.from_numpy(x.T.copy())
+    U = W.rotation_velocity(xt).numpy().T.copy()
+    c0 = (W.slotted_cylinder(xt) + W.cone(xt) + W.hill(xt)).numpy()
+    ch, X, _ = m.trace(U, None, c0, 2 * np.pi, 6283, threads=8)
+    e = c0 - ch
+    h0 = np.sqrt(m.mass_quadform(e, e))
+    one = np.ones(m.N)
+    dm = m.mass_quadform(one, ch) / m.mass_quadform(one, c0) - 1
+    assert h0 < 10 * gold["H0"] and abs(dm) < 1e-12
+    assert abs((ch.max() - ch.min()) - gold["var"]) < 1e-4
