@@ -173,8 +173,8 @@ mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec,
         delete c;
         return MMOC_E_HIP;
     }
-    if (dev_alloc(c, &c->stats_d, mmoc::ST_COUNT, "stats") != MMOC_OK ||
-        hipMemset(c->stats_d, 0, sizeof(unsigned long long) * mmoc::ST_COUNT) != hipSuccess) {
+    if (dev_alloc(c, &c->stats_d, (size_t)mmoc::ST_COUNT * mmoc::kStatSpread, "stats") != MMOC_OK ||
+        hipMemset(c->stats_d, 0, sizeof(unsigned long long) * mmoc::ST_COUNT * mmoc::kStatSpread) != hipSuccess) {
         free_all(c);
         delete c;
         return MMOC_E_HIP;
@@ -573,9 +573,17 @@ mmoc_status mmoc_trace_step(mmoc_ctx* c, double dt, int substeps, void* c_hat, d
 mmoc_status mmoc_get_stats(mmoc_ctx* c, mmoc_stats* out)
 {
     if (!c || !out) return MMOC_E_ARG;
-    unsigned long long h[mmoc::ST_COUNT];
-    HIPCHK(c, hipMemcpyAsync(h, c->stats_d, sizeof h, hipMemcpyDeviceToHost, c->stream), "read stats");
+    unsigned long long w[mmoc::ST_COUNT * mmoc::kStatSpread];
+    HIPCHK(c, hipMemcpyAsync(w, c->stats_d, sizeof w, hipMemcpyDeviceToHost, c->stream), "read stats");
     HIPCHK(c, hipStreamSynchronize(c->stream), "read stats");
+    // each counter is spread over kStatSpread words: sum them (max for the residual bits)
+    unsigned long long h[mmoc::ST_COUNT] = {};
+    for (int k = 0; k < mmoc::ST_COUNT; ++k)
+        for (int j = 0; j < mmoc::kStatSpread; ++j) {
+            const unsigned long long v = w[k * mmoc::kStatSpread + j];
+            if (k == mmoc::ST_MAXRES_BITS) h[k] = v > h[k] ? v : h[k];
+            else h[k] += v;
+        }
     out->n_particles = (int64_t)h[mmoc::ST_PARTICLES];
     out->n_outside = (int64_t)h[mmoc::ST_OUTSIDE];
     out->n_multi_hop = (int64_t)h[mmoc::ST_MULTIHOP];
@@ -593,7 +601,8 @@ mmoc_status mmoc_get_stats(mmoc_ctx* c, mmoc_stats* out)
 mmoc_status mmoc_reset_stats(mmoc_ctx* c)
 {
     if (!c) return MMOC_E_ARG;
-    HIPCHK(c, hipMemsetAsync(c->stats_d, 0, sizeof(unsigned long long) * mmoc::ST_COUNT, c->stream), "reset stats");
+    HIPCHK(c, hipMemsetAsync(c->stats_d, 0, sizeof(unsigned long long) * mmoc::ST_COUNT * mmoc::kStatSpread, c->stream),
+           "reset stats");
     return MMOC_OK;
 }
 

@@ -31,7 +31,12 @@ __host__ __device__ inline uint64_t pack_owned(uint32_t M, uint32_t I, uint32_t 
     return ((uint64_t)M << 36) | ((uint64_t)I << 24) | ((uint64_t)J << 12) | (uint64_t)K;
 }
 
-// Statistic counters kept in device memory (uint64 each).
+// Statistic counters kept in device memory.  Each counter is a row of
+// kStatSpread uint64 words; a block adds into word blockIdx % kStatSpread of
+// the row, so that the per-wave atomics of thousands of waves finishing
+// together do not queue on one address.  The host sums a row (max for
+// ST_MAXRES_BITS) when it reads the statistics.
+constexpr int kStatSpread = 64;
 enum StatSlot {
     ST_PARTICLES = 0,
     ST_OUTSIDE,

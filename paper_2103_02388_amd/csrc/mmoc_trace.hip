@@ -75,20 +75,20 @@ struct Geo64 {
     double pn[3];
     double pc;
 
-    __device__ __forceinline__ void load(const MacroGeo* __restrict__ g, int M)
+    template <typename P>
+    __device__ __forceinline__ void load(P g, int M)
     {
-        const MacroGeo& G = g[M];
 #pragma unroll
-        for (int i = 0; i < DIM; ++i) v0[i] = G.v0[i];
+        for (int i = 0; i < DIM; ++i) v0[i] = g[M].v0[i];
 #pragma unroll
         for (int r = 0; r < DIM; ++r)
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) bi[r][c] = G.binv[r * 3 + c];
+            for (int c = 0; c < DIM; ++c) bi[r][c] = g[M].binv[r * 3 + c];
         if constexpr (BLEND) {
-            pn[0] = G.pn[0];
-            pn[1] = G.pn[1];
-            pn[2] = G.pn[2];
-            pc = G.pc;
+            pn[0] = g[M].pn[0];
+            pn[1] = g[M].pn[1];
+            pn[2] = g[M].pn[2];
+            pc = g[M].pc;
         }
     }
 
@@ -113,18 +113,45 @@ struct Geo64 {
     {
         double p[DIM];
         offset(y, p);
-        double sum = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            double acc = 0.0;
+            double acc = bi[a][0] * p[0];
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) acc = fma(bi[a][i], p[i], acc);
+            for (int i = 1; i < DIM; ++i) acc = fma(bi[a][i], p[i], acc);
             s[a] = acc;
-            sum += acc;
         }
+        double sum = s[0];
+#pragma unroll
+        for (int a = 1; a < DIM; ++a) sum += s[a];
         return 1.0 - sum;
     }
 };
+
+// Reference coordinates of y in macro M, the geometry read afresh for each
+// evaluation instead of being kept in registers across the loop.  When every
+// active lane of the wave is in the same macro (the common case) the record
+// is read through scalar loads into scalar registers; otherwise each lane
+// reads its own (an L1/L2 hit: the table is small).
+typedef __attribute__((address_space(4))) const MacroGeo* ConstGeo;
+
+template <int DIM, int BLEND>
+__device__ __forceinline__ double ref_at(const MacroGeo* __restrict__ geo, int M, const double* y, double* s)
+{
+    const int M0 = __builtin_amdgcn_readfirstlane(M);
+    Geo64<DIM, BLEND> G;
+    if (__ballot(M != M0) == 0) {
+        // the table is read-only for the whole launch: a load through the
+        // constant address space at a uniform address is a scalar load
+        G.load((ConstGeo)geo, M0);
+        const double l0 = G.ref(y, s);
+        // keeps the two branches apart, so that this one computes with the
+        // geometry in scalar registers instead of copying it to vector ones
+        __asm__ volatile("");
+        return l0;
+    }
+    G.load(geo, M);
+    return G.ref(y, s);
+}
 
 template <int DIM, typename R>
 __device__ __forceinline__ R lam_min(R l0, const R* s)
@@ -144,7 +171,7 @@ __device__ __forceinline__ R lam_min(R l0, const R* s)
 // that the hot loop never spills; returns the macro in bits 0-26 and lane
 // flags above.
 template <int DIM, int BLEND>
-__device__ __noinline__ unsigned walk64(const MacroGeo* __restrict__ geo, int nm, int max_hops, double eps, int M,
+__device__ __noinline__ __attribute__((pure)) unsigned walk64(const MacroGeo* __restrict__ geo, int nm, int max_hops, double eps, int M,
                                         double y0, double y1, double y2)
 {
     const double y[3] = {y0, y1, y2};
@@ -208,10 +235,11 @@ __device__ __forceinline__ int tet_n(int x) { return (x * (x + 1) * (x + 2)) / 6
 // coordinates w (w_d = s_d, w_a = s_a + w_{a+1}), then the P2 shape
 // functions at the (possibly unclamped) point.  A point outside the macro
 // selects its element from the clamped, renormalised barycentrics and is
-// evaluated by extrapolating that element.  Returns the smallest distance of
-// the selection coordinates W = n w from a tie (an integer, or another
-// coordinate), which the mixed-precision path compares with its band.
-template <int DIM, typename R>
+// evaluated by extrapolating that element.  With GAP, returns the smallest
+// distance of the selection coordinates W = n w from a tie (an integer, or
+// another coordinate), which the mixed-precision path compares with its
+// micro band (1 without GAP).
+template <int DIM, typename R, bool GAP = false>
 __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM, R>& st)
 {
     R ssel[DIM];
@@ -246,7 +274,7 @@ __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM,
         k[i] = (int)kc;
         f[i] = W[i] - kc;
         fu[i] = Wu[i] - kc;
-        gap = fmin(gap, fmin(fabs(f[i]), fabs(R(1) - f[i])));
+        if constexpr (GAP) gap = fmin(gap, fmin(fabs(f[i]), fabs(R(1) - f[i])));
     }
     // rank of each axis in the descending order of f (ties: lower axis first)
     int r[3] = {0, 0, 0};
@@ -258,13 +286,13 @@ __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM,
         g[0] = r[0] == 0 ? fu[0] : (r[1] == 0 ? fu[1] : fu[2]);
         g[1] = r[0] == 1 ? fu[0] : (r[1] == 1 ? fu[1] : fu[2]);
         g[2] = r[0] == 2 ? fu[0] : (r[1] == 2 ? fu[1] : fu[2]);
-        gap = fmin(gap, fmin(fabs(f[0] - f[1]), fmin(fabs(f[0] - f[2]), fabs(f[1] - f[2]))));
+        if constexpr (GAP) gap = fmin(gap, fmin(fabs(f[0] - f[1]), fmin(fabs(f[0] - f[2]), fabs(f[1] - f[2]))));
     } else {
         r[0] = f[1] > f[0];
         r[1] = f[0] >= f[1];
         g[0] = r[0] == 0 ? fu[0] : fu[1];
         g[1] = r[0] == 1 ? fu[0] : fu[1];
-        gap = fmin(gap, fabs(f[0] - f[1]));
+        if constexpr (GAP) gap = fmin(gap, fabs(f[0] - f[1]));
     }
     R mu[DIM + 1];
     mu[0] = R(1) - g[0];
@@ -462,6 +490,13 @@ __device__ __forceinline__ int own_lat_idx(uint64_t e)
     else return tet_n(I) + tri_n(J) + K;
 }
 
+// this block's word of statistic row `which`
+__device__ __forceinline__ unsigned long long* stat_word(unsigned long long* stats, int which)
+{
+    return stats + which * kStatSpread + (blockIdx.x & (kStatSpread - 1));
+}
+
+// per-wave counts of the lane flags, one atomic per non-zero count
 __device__ __forceinline__ void count_flags(unsigned long long* stats, bool active, unsigned flags)
 {
     const unsigned long long nact = __popcll(__ballot(active));
@@ -471,20 +506,37 @@ __device__ __forceinline__ void count_flags(unsigned long long* stats, bool acti
     const unsigned long long nt = __popcll(__ballot((flags & LF_TIEBAND) != 0));
     const unsigned long long nn = __popcll(__ballot((flags & LF_NAN) != 0));
     if ((threadIdx.x & 63) == 0) {
-        if (nact) atomicAdd(stats + ST_PARTICLES, nact);
-        if (no) atomicAdd(stats + ST_OUTSIDE, no);
-        if (nm) atomicAdd(stats + ST_MULTIHOP, nm);
-        if (nb) atomicAdd(stats + ST_BRUTE, nb);
-        if (nt) atomicAdd(stats + ST_TIEBAND, nt);
-        if (nn) atomicAdd(stats + ST_NAN, nn);
+        if (nact) atomicAdd(stat_word(stats, ST_PARTICLES), nact);
+        if (no) atomicAdd(stat_word(stats, ST_OUTSIDE), no);
+        if (nm) atomicAdd(stat_word(stats, ST_MULTIHOP), nm);
+        if (nb) atomicAdd(stat_word(stats, ST_BRUTE), nb);
+        if (nt) atomicAdd(stat_word(stats, ST_TIEBAND), nt);
+        if (nn) atomicAdd(stat_word(stats, ST_NAN), nn);
     }
+}
+
+// Appends the lanes with `take` to a list: one atomic per wave on the list
+// length, each lane's position from its rank among the taking lanes.
+// Returns the lane's index into the list (meaningful where take is set).
+__device__ __forceinline__ unsigned long long wave_append(unsigned long long* len, bool take)
+{
+    const unsigned long long mask = __ballot(take);
+    if (mask == 0) return 0;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(len, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    const unsigned long long below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
+    return base + (unsigned long long)__popcll(below);
 }
 
 // --------------------------------------------------------------- fp64 trace
 
 template <int DIM, int NLEV, int BLEND>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP64)))
-void trace_fp64_kernel(const TraceArgs<double> A)
+void trace_fp64_kernel(const TraceArgs<double> A, const MacroGeo* __restrict__ geo, double* __restrict__ c_hat,
+                       double* __restrict__ X, unsigned long long* __restrict__ stats)
 {
     const int64_t t = logical_block() * kTB + threadIdx.x;
     const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
@@ -494,9 +546,7 @@ void trace_fp64_kernel(const TraceArgs<double> A)
         const uint64_t e = A.owned[pid];
         int M;
         double Y[DIM];
-        dof_position<DIM, BLEND>(A.geo, e, A.level_n, M, Y);
-        Geo64<DIM, BLEND> G;
-        G.load(A.geo, M);
+        dof_position<DIM, BLEND>(geo, e, A.level_n, M, Y);
         uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
         const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
         const double h = A.dt / (double)A.substeps;
@@ -519,19 +569,15 @@ void trace_fp64_kernel(const TraceArgs<double> A)
                     // the particle sits on its own DoF
                     nodal_vel<DIM, NLEV, double, double>(A, own_slot, theta, ks);
                 } else {
-                    l0 = G.ref(y, s);
+                    l0 = ref_at<DIM, BLEND>(geo, M, y, s);
                     lmin = lam_min<DIM, double>(l0, s);
                     if (lmin < -A.eps_in) {
-                        const unsigned r = walk64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, y[0], y[1],
+                        const unsigned r = walk64<DIM, BLEND>(geo, A.nm, A.max_hops, A.eps_in, M, y[0], y[1],
                                                              DIM == 3 ? y[DIM - 1] : 0.0);
                         flags |= r >> 27;
-                        const int M2 = (int)(r & ((1u << 27) - 1));
-                        if (M2 != M) {
-                            M = M2;
-                            G.load(A.geo, M);
-                            mbase = (uint32_t)M * (uint32_t)A.npm;
-                        }
-                        l0 = G.ref(y, s);
+                        M = (int)(r & ((1u << 27) - 1));
+                        mbase = (uint32_t)M * (uint32_t)A.npm;
+                        l0 = ref_at<DIM, BLEND>(geo, M, y, s);
                         lmin = lam_min<DIM, double>(l0, s);
                     }
                     micro<DIM, double>(s, l0, lmin, A.level_n, st);
@@ -550,19 +596,15 @@ void trace_fp64_kernel(const TraceArgs<double> A)
             for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - h6 * acc[i];
         }
         // step (iii): the scalar at the departure point
-        l0 = G.ref(Y, s);
+        l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
         lmin = lam_min<DIM, double>(l0, s);
         if (lmin < -A.eps_in) {
             const unsigned r =
-                walk64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, Y[0], Y[1], DIM == 3 ? Y[DIM - 1] : 0.0);
+                walk64<DIM, BLEND>(geo, A.nm, A.max_hops, A.eps_in, M, Y[0], Y[1], DIM == 3 ? Y[DIM - 1] : 0.0);
             flags |= r >> 27;
-            const int M2 = (int)(r & ((1u << 27) - 1));
-            if (M2 != M) {
-                M = M2;
-                G.load(A.geo, M);
-                mbase = (uint32_t)M * (uint32_t)A.npm;
-            }
-            l0 = G.ref(Y, s);
+            M = (int)(r & ((1u << 27) - 1));
+            mbase = (uint32_t)M * (uint32_t)A.npm;
+            l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
             lmin = lam_min<DIM, double>(l0, s);
         }
         micro<DIM, double>(s, l0, lmin, A.level_n, st);
@@ -571,13 +613,13 @@ void trace_fp64_kernel(const TraceArgs<double> A)
 #pragma unroll
         for (int i = 0; i < DIM; ++i) bad |= Y[i] != Y[i];
         if (bad) flags |= LF_NAN;
-        if (A.c_hat) A.c_hat[pid] = v;
-        if (A.X) {
+        if (c_hat) c_hat[pid] = v;
+        if (X) {
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) A.X[(int64_t)i * A.xstride + pid] = Y[i];
+            for (int i = 0; i < DIM; ++i) X[(int64_t)i * A.xstride + pid] = Y[i];
         }
     }
-    count_flags(A.stats, active, flags);
+    count_flags(stats, active, flags);
 }
 
 // --------------------------------------------------------- fp32 mixed trace
@@ -586,48 +628,71 @@ template <int DIM, int BLEND>
 struct Geo32 {
     double v0[DIM];
     float bi[DIM][DIM];
+    double pn[3];
+    double pc;
 
-    __device__ __forceinline__ void load(const MacroGeo* __restrict__ g, int M)
+    template <typename P>
+    __device__ __forceinline__ void load(P g, int M)
     {
-        const MacroGeo& G = g[M];
 #pragma unroll
-        for (int i = 0; i < DIM; ++i) v0[i] = G.v0[i];
+        for (int i = 0; i < DIM; ++i) v0[i] = g[M].v0[i];
 #pragma unroll
         for (int r = 0; r < DIM; ++r)
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) bi[r][c] = G.binvf[r * 3 + c];
+            for (int c = 0; c < DIM; ++c) bi[r][c] = g[M].binvf[r * 3 + c];
+        if constexpr (BLEND) {
+            pn[0] = g[M].pn[0];
+            pn[1] = g[M].pn[1];
+            pn[2] = g[M].pn[2];
+            pc = g[M].pc;
+        }
+    }
+
+    // Reference coordinates in float32: the offset from the macro origin is
+    // formed in float64 (the only float64 work of an ordinary stage), then
+    // rounded and mapped with the float32 inverse.
+    __device__ __forceinline__ float ref(const double* y, float* s) const
+    {
+        float p[DIM];
+        if constexpr (BLEND) {
+            const double nz = pn[0] * y[0] + pn[1] * y[1] + pn[2] * y[2];
+            const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+            const double f = pc * r / nz;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) p[i] = (float)fma(y[i], f, -v0[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) p[i] = (float)(y[i] - v0[i]);
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            float acc = bi[a][0] * p[0];
+#pragma unroll
+            for (int i = 1; i < DIM; ++i) acc = fmaf(bi[a][i], p[i], acc);
+            s[a] = acc;
+        }
+        float sum = s[0];
+#pragma unroll
+        for (int a = 1; a < DIM; ++a) sum += s[a];
+        return 1.0f - sum;
     }
 };
 
-// Reference coordinates in float32: the offset from the macro origin is
-// formed in float64 (the only float64 work of an ordinary stage), then
-// rounded and mapped with the float32 inverse.
+// float32 reference coordinates of y in macro M (geometry read per
+// evaluation, through scalar loads when the wave is in one macro)
 template <int DIM, int BLEND>
-__device__ __forceinline__ float ref32(const Geo32<DIM, BLEND>& G, const MacroGeo* __restrict__ geo, int M,
-                                       const double* y, float* s)
+__device__ __forceinline__ float ref32_at(const MacroGeo* __restrict__ geo, int M, const double* y, float* s)
 {
-    float p[DIM];
-    if constexpr (BLEND) {
-        const MacroGeo& Gm = geo[M];
-        const double nz = Gm.pn[0] * y[0] + Gm.pn[1] * y[1] + Gm.pn[2] * y[2];
-        const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-        const double f = Gm.pc * r / nz;
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) p[i] = (float)fma(y[i], f, -G.v0[i]);
-    } else {
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) p[i] = (float)(y[i] - G.v0[i]);
+    const int M0 = __builtin_amdgcn_readfirstlane(M);
+    Geo32<DIM, BLEND> G;
+    if (__ballot(M != M0) == 0) {
+        G.load((ConstGeo)geo, M0);
+        const float l0 = G.ref(y, s);
+        __asm__ volatile("");
+        return l0;
     }
-    float sum = 0.0f;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) acc = fmaf(G.bi[a][i], p[i], acc);
-        s[a] = acc;
-        sum += acc;
-    }
-    return 1.0f - sum;
+    G.load(geo, M);
+    return G.ref(y, s);
 }
 
 // The float64 re-evaluation of one location: with `walk`, the macro walk in
@@ -665,11 +730,11 @@ __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int 
 // Near a boundary face there is no second macro to choose: the point stays,
 // and its element is selected from the clamped barycentrics as in float64.
 template <int DIM, int BLEND>
-__device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, Geo32<DIM, BLEND>& G, uint32_t& mbase,
-                                         const double* y, Stencil<DIM, float>& st, unsigned& flags)
+__device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint32_t& mbase, const double* y,
+                                         Stencil<DIM, float>& st, unsigned& flags)
 {
     float s[DIM];
-    const float l0 = ref32<DIM, BLEND>(G, A.geo, M, y, s);
+    const float l0 = ref32_at<DIM, BLEND>(A.geo, M, y, s);
     const float lmin = lam_min<DIM, float>(l0, s);
     bool macro_redo = lmin < A.eps32_macro;
     if (macro_redo && lmin > -A.eps32_macro) {
@@ -685,8 +750,12 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, Geo3
     }
     bool redo = macro_redo;
     if (!macro_redo) {
-        const float gap = micro<DIM, float>(s, l0, lmin, A.level_n, st);
-        redo = gap < A.eps32_micro * (float)A.level_n;
+        if (A.eps32_micro > 0.0f) {
+            const float gap = micro<DIM, float, true>(s, l0, lmin, A.level_n, st);
+            redo = gap < A.eps32_micro * (float)A.level_n;
+        } else {
+            micro<DIM, float>(s, l0, lmin, A.level_n, st);
+        }
     }
     if (redo) {
         if (!macro_redo || lmin > -A.eps32_macro) flags |= LF_TIEBAND;
@@ -694,12 +763,8 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, Geo3
         const unsigned r = locate64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, A.level_n, macro_redo, y[0],
                                                 y[1], DIM == 3 ? y[DIM - 1] : 0.0, &s64);
         flags |= r >> 27;
-        const int M2 = (int)(r & ((1u << 27) - 1));
-        if (M2 != M) {
-            M = M2;
-            G.load(A.geo, M);
-            mbase = (uint32_t)M * (uint32_t)A.npm;
-        }
+        M = (int)(r & ((1u << 27) - 1));
+        mbase = (uint32_t)M * (uint32_t)A.npm;
         st = s64;
     }
 }
@@ -717,8 +782,6 @@ void trace_fp32_kernel(const TraceArgs<float> A)
         int M;
         double Y[DIM];
         dof_position<DIM, BLEND>(A.geo, e, A.level_n, M, Y);
-        Geo32<DIM, BLEND> G;
-        G.load(A.geo, M);
         uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
         const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
         const double hd = A.dt / (double)A.substeps;
@@ -740,7 +803,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
                 if (j == 0 && stg == 0) {
                     nodal_vel<DIM, NLEV, float, float>(A, own_slot, theta, ks);
                 } else {
-                    locate32<DIM, BLEND>(A, M, G, mbase, y, st, flags);
+                    locate32<DIM, BLEND>(A, M, mbase, y, st, flags);
                     gather_vel<DIM, NLEV, float, float>(A, mbase, st, theta, ks);
                 }
                 const float wst = (stg == 0 || stg == 3) ? 1.0f : 2.0f;
@@ -755,7 +818,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
 #pragma unroll
             for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - (double)(h6 * acc[i]);
         }
-        locate32<DIM, BLEND>(A, M, G, mbase, Y, st, flags);
+        locate32<DIM, BLEND>(A, M, mbase, Y, st, flags);
         const float v = gather_scalar<DIM, float, float>(A, mbase, st);
         bool bad = v != v;
 #pragma unroll
@@ -785,18 +848,15 @@ __global__ __launch_bounds__(kTB) void scalar_eval_fp64_kernel(const TraceArgs<d
         double Y[DIM];
 #pragma unroll
         for (int i = 0; i < DIM; ++i) Y[i] = A.X[(int64_t)i * A.xstride + t];
-        Geo64<DIM, BLEND> G;
-        G.load(A.geo, M);
         double s[DIM];
-        double l0 = G.ref(Y, s);
+        double l0 = ref_at<DIM, BLEND>(A.geo, M, Y, s);
         double lmin = lam_min<DIM, double>(l0, s);
         if (lmin < -A.eps_in) {
             const unsigned r =
                 walk64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, Y[0], Y[1], DIM == 3 ? Y[DIM - 1] : 0.0);
             flags |= r >> 27;
             M = (int)(r & ((1u << 27) - 1));
-            G.load(A.geo, M);
-            l0 = G.ref(Y, s);
+            l0 = ref_at<DIM, BLEND>(A.geo, M, Y, s);
             lmin = lam_min<DIM, double>(l0, s);
         }
         Stencil<DIM, double> st;
@@ -817,12 +877,10 @@ __global__ __launch_bounds__(kTB) void scalar_eval_fp32_kernel(const TraceArgs<f
     double Y[DIM];
 #pragma unroll
     for (int i = 0; i < DIM; ++i) Y[i] = A.X[(int64_t)i * A.xstride + t];
-    Geo32<DIM, BLEND> G;
-    G.load(A.geo, M);
     uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
     Stencil<DIM, float> st;
     unsigned flags = 0;
-    locate32<DIM, BLEND>(A, M, G, mbase, Y, st, flags);
+    locate32<DIM, BLEND>(A, M, mbase, Y, st, flags);
     A.c_hat[t] = gather_scalar<DIM, float, float>(A, mbase, st);
 }
 
@@ -878,21 +936,32 @@ __global__ __launch_bounds__(256) void residual_kernel(int dim, int64_t n, int t
                                                        double tol, unsigned char* tile_flag, unsigned long long* stats)
 {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if ((unsigned long long)k >= *n_ids) return;
-    const int64_t i = ids[k];
-    double r = 0.0;
-    for (int d = 0; d < dim; ++d) {
-        const double a = X[(int64_t)d * n + i], b = Xrk[(int64_t)d * n + i];
-        const double e = fabs(a - b);
-        r = (e > r || e != e) ? e : r;
-        X[(int64_t)d * n + i] = b;  // a checked particle keeps its RK4 result
+    const bool active = (unsigned long long)k < *n_ids;
+    unsigned long long bits = 0;  // the residual's bits: non-negative doubles order like their bits
+    if (active) {
+        const int64_t i = ids[k];
+        double r = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            const double a = X[(int64_t)d * n + i], b = Xrk[(int64_t)d * n + i];
+            const double e = fabs(a - b);
+            r = (e > r || e != e) ? e : r;
+            X[(int64_t)d * n + i] = b;  // a checked particle keeps its RK4 result
+        }
+        if (!(r <= 0.5 * tol)) tile_flag[i / tile] = 1;
+        if (r != r) r = INFINITY;
+        __builtin_memcpy(&bits, &r, sizeof bits);
     }
-    if (!(r <= 0.5 * tol)) tile_flag[i / tile] = 1;
-    if (r != r) r = INFINITY;
-    unsigned long long bits;
-    __builtin_memcpy(&bits, &r, sizeof bits);
-    atomicMax(stats + ST_MAXRES_BITS, bits);  // non-negative doubles order like their bits
-    atomicAdd(stats + ST_CHECKED, 1ull);
+    // one atomic per wave for the count and the largest residual
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(bits, off, 64);
+        bits = o > bits ? o : bits;
+    }
+    const unsigned long long cnt = __popcll(__ballot(active));
+    if ((threadIdx.x & 63) == 0 && cnt) {
+        atomicMax(stat_word(stats, ST_MAXRES_BITS), bits);
+        atomicAdd(stat_word(stats, ST_CHECKED), cnt);
+    }
 }
 
 __global__ __launch_bounds__(256) void fallback_list_kernel(int64_t n, int tile, const unsigned char* tile_flag,
@@ -900,11 +969,11 @@ __global__ __launch_bounds__(256) void fallback_list_kernel(int64_t n, int tile,
                                                             unsigned long long* n_ids, unsigned long long* stats)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    if (tile_flag[i / tile] && !checked[i]) {
-        ids[atomicAdd(n_ids, 1ull)] = (int32_t)i;
-        atomicAdd(stats + ST_FALLBACK, 1ull);
-    }
+    const bool take = i < n && tile_flag[i / tile] && !checked[i];
+    const unsigned long long pos = wave_append(n_ids, take);
+    if (take) ids[pos] = (int32_t)i;
+    const unsigned long long cnt = __popcll(__ballot(take));
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(stat_word(stats, ST_FALLBACK), cnt);
 }
 
 inline unsigned grid_xcd(int64_t n)
@@ -922,14 +991,14 @@ hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hip
     const dim3 grid(grid_xcd(a.n)), block(kTB);
     const bool st = a.nlev == 1;
     if (dim == 2 && !blend) {
-        if (st) trace_fp64_kernel<2, 1, 0><<<grid, block, 0, s>>>(a);
-        else trace_fp64_kernel<2, 2, 0><<<grid, block, 0, s>>>(a);
+        if (st) trace_fp64_kernel<2, 1, 0><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        else trace_fp64_kernel<2, 2, 0><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
     } else if (dim == 3 && !blend) {
-        if (st) trace_fp64_kernel<3, 1, 0><<<grid, block, 0, s>>>(a);
-        else trace_fp64_kernel<3, 2, 0><<<grid, block, 0, s>>>(a);
+        if (st) trace_fp64_kernel<3, 1, 0><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        else trace_fp64_kernel<3, 2, 0><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
     } else if (dim == 3 && blend) {
-        if (st) trace_fp64_kernel<3, 1, 1><<<grid, block, 0, s>>>(a);
-        else trace_fp64_kernel<3, 2, 1><<<grid, block, 0, s>>>(a);
+        if (st) trace_fp64_kernel<3, 1, 1><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        else trace_fp64_kernel<3, 2, 1><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
     } else {
         return hipErrorNotSupported;
     }
