@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--substeps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--paths", default="fp64,fp32", help="tracer paths to time (fp64 is the headline)")
+    ap.add_argument("--paths", default="fp64,fp32,fp32f", help="tracer paths to time (fp64 is the headline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (10 times), to scale HBM counters")
     args = ap.parse_args()
@@ -160,6 +160,14 @@ def main():
                              "speedup_vs_fp64_trace": r["kernel_ms"] / f["kernel_ms"],
                              "error_bound_vs_oracle": 1e-5,
                              "tieband_fraction": f["stats"]["n_tieband"] / max(1, f["stats"]["n_particles"])}
+    if "fp32f" in results:
+        f = results["fp32f"]
+        out["fp32_fields"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "kernel_ms": f["kernel_ms"],
+                              "trace_only_particles_per_s": N / (f["kernel_ms"] * 1e-3),
+                              "speedup_vs_fp64_step": f["value"] / r["value"],
+                              "speedup_vs_fp64_trace": r["kernel_ms"] / f["kernel_ms"],
+                              "error_bound_vs_oracle": 1e-6,
+                              "note": "float32 field records, float64 arithmetic"}
     if not args.no_surrogate:
         out["surrogate"] = time_surrogate(wl, S, min(args.steps, 50), min(args.warmup, 5), results)
     if not args.no_cpu_baseline:
@@ -172,7 +180,7 @@ def time_path(wl, path, S, steps, warmup):
     from paper_2103_02388_amd import mmoc
     from paper_2103_02388_amd import workloads as W
 
-    prec = mmoc.MMOC_FP64 if path == "fp64" else mmoc.MMOC_FP32_MIXED
+    prec = {"fp64": mmoc.MMOC_FP64, "fp32": mmoc.MMOC_FP32_MIXED, "fp32f": mmoc.MMOC_FP32_FIELDS}[path]
     tr = mmoc.Tracer.from_workload(wl, precision=prec)
     N = tr.N
     x = tr.dof_coords()

@@ -55,21 +55,27 @@ typedef enum {
     MMOC_E_STATE = -3,       /* call out of order (e.g. trace before fields are set) */
     MMOC_E_HIP = -4,         /* HIP runtime error */
     MMOC_E_NOMEM = -5,       /* device allocation failed */
-    MMOC_E_UNSUPPORTED = -6  /* combination not built (e.g. 2D shell blending) */
+    MMOC_E_UNSUPPORTED = -6  /* combination not built (e.g. P1 on a blended mesh) */
 } mmoc_status;
 
 typedef enum {
-    MMOC_FP64 = 0,       /* every stage in float64 */
-    MMOC_FP32_MIXED = 1  /* stages, location and interpolation in float32 on float32 field
-                            copies; location decisions within eps of a macro or micro face
-                            re-taken in float64; departure points accumulated in float64 */
+    MMOC_FP64 = 0,        /* every stage in float64 */
+    MMOC_FP32_MIXED = 1,  /* stages, location and interpolation in float32 on float32 field
+                             copies; location decisions within eps of a macro or micro face
+                             re-taken in float64; departure points accumulated in float64 */
+    MMOC_FP32_FIELDS = 2  /* float32 field records (half the gather bytes of MMOC_FP64),
+                             every operation in float64; chat is written as float32.  The
+                             only error against float64 is the rounding of the stored
+                             nodal values. */
 } mmoc_precision;
 
 typedef enum {
     MMOC_BLEND_NONE = 0,         /* physical domain = computational domain */
-    MMOC_BLEND_SHELL_RADIAL = 1  /* spherical shell: each macro's column (its three unit
-                                    directions span a plane n.x = c) is mapped radially,
-                                    Phi(x) = x (n.x)/(c|x|) (Sec. 2.1 blending function) */
+    MMOC_BLEND_SHELL_RADIAL = 1  /* radial blending of a spherical shell (3D) or an annulus
+                                    (2D): each macro's column (the tips of its d unit
+                                    directions span a plane, in 2D a line, n.x = c) is
+                                    mapped radially, Phi(x) = x (n.x)/(c|x|) (Sec. 2.1
+                                    blending function; Sec. 4 annulus) */
 } mmoc_blend;
 
 typedef struct {
@@ -83,7 +89,10 @@ typedef struct {
                           re-located.  Float32 rounding of the lattice coordinates
                           is about n * 1e-6; 2^-18 is a sound non-zero band) */
     int max_hops;      /* walk hops before brute-force location (default 64) */
-    int reserved[4];
+    int order;         /* element order of the fields and DoFs: 2 = P2 (default; 0 also
+                          means 2), 1 = P1, the micro vertices (Sec. 3.1: P1 and P2
+                          Lagrange elements).  P1 is not built for blended meshes. */
+    int reserved[3];
 } mmoc_options;
 
 typedef struct {
@@ -120,7 +129,8 @@ mmoc_status mmoc_set_stream(mmoc_ctx* ctx, void* hip_stream);
  * do).  Derives face neighbours, the unique DoF numbering and the per-macro
  * block layout, and uploads them.  May be called once per context.
  * Errors: MMOC_E_MESH for degenerate or non-manifold meshes or non-conforming
- * vertex orders, MMOC_E_UNSUPPORTED for shell blending with dim != 3. */
+ * vertex orders or a blended macro that does not span exactly dim radial
+ * directions, MMOC_E_UNSUPPORTED for P1 elements on a blended mesh. */
 mmoc_status mmoc_upload_mesh(mmoc_ctx* ctx, int n_vertices, const double* vertex_xyz,
                              int n_macros, const int32_t* macro_vertices, mmoc_blend blend);
 
@@ -132,11 +142,13 @@ mmoc_status mmoc_num_dofs(const mmoc_ctx* ctx, int64_t* n_unique, int64_t* n_blo
  * memory owned by the caller (Sec. 2.3.1 step (i)). */
 mmoc_status mmoc_dof_coords(mmoc_ctx* ctx, double* xyz_dev);
 
-/* Sets velocity level 0 (u_h^n at t_n) or 1 (u_h^{n+1} at t_{n+1}) from a
- * unique-layout SoA [dim][n_unique] float64 device array (eq.
- * linear-interpolation).  The values are copied into the library's block
- * layout (float32 for MMOC_FP32_MIXED); the caller may free u_dev once the
- * stream has passed this call. */
+/* Sets velocity level `level` from a unique-layout SoA [dim][n_unique]
+ * float64 device array (eq. linear-interpolation).  With the default two
+ * levels, level 0 is u_h^n at t_n and level 1 u_h^{n+1} at t_{n+1};
+ * mmoc_set_level_count holds more (levels l at equally spaced times, l = 0
+ * the oldest).  The values are copied into the library's block layout
+ * (float32 for MMOC_FP32_MIXED and MMOC_FP32_FIELDS); the caller may free
+ * u_dev once the stream has passed this call. */
 mmoc_status mmoc_set_velocity(mmoc_ctx* ctx, int level, const double* u_dev);
 
 /* on != 0: the velocity is stationary; only level 0 is used (setting level 1
@@ -144,9 +156,10 @@ mmoc_status mmoc_set_velocity(mmoc_ctx* ctx, int level, const double* u_dev);
  * back to two levels requires level 1 to be set again. */
 mmoc_status mmoc_set_stationary(mmoc_ctx* ctx, int on);
 
-/* Makes level 1 the new level 0 (u^{n+1} becomes u^n for the next step, no
- * copy).  Level 1 must be set again before the next trace; the scalar keeps
- * its value until mmoc_set_scalar is called. */
+/* Makes level l + 1 the new level l for every l (u^{n+1} becomes u^n for the
+ * next step; the levels form a ring, nothing is copied).  The last level
+ * must be set again before it is used; the scalar keeps its value until
+ * mmoc_set_scalar is called. */
 mmoc_status mmoc_swap_velocity_levels(mmoc_ctx* ctx);
 
 /* Sets the scalar c_h^n from a unique-layout [n_unique] float64 device array
@@ -156,15 +169,51 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* ctx, const double* c_dev);
 /* One MMOC advection step of length dt > 0 with substeps >= 1 RK4 sub-steps
  * (Alg. 1 departure-point and advection lines).  c_hat_dev receives
  * chat_i = c_h^n(X_i) in unique order: double* [n_unique] for MMOC_FP64,
- * float* [n_unique] for MMOC_FP32_MIXED.  X_dev (may be NULL) receives the
- * departure points, SoA [dim][n_unique] float64 (physical coordinates).
+ * float* [n_unique] for MMOC_FP32_MIXED and MMOC_FP32_FIELDS.  X_dev (may be
+ * NULL) receives the departure points, SoA [dim][n_unique] float64 (physical coordinates).
  * Points that leave the domain are evaluated by extrapolating the boundary
  * element reached by the walk (counted in n_outside). */
 mmoc_status mmoc_trace_step(mmoc_ctx* ctx, double dt, int substeps, void* c_hat_dev, double* X_dev);
 
+/* Holds `levels` velocity levels (2..65536; default 2) for traces across
+ * several time steps (look-back b > 1 with a time-dependent velocity,
+ * Sec. 2.3.3).  Reallocates the levels: every level must be set again. */
+mmoc_status mmoc_set_level_count(mmoc_ctx* ctx, int levels);
+
+/* A trace across n_int >= 1 time steps of length dt (look-back, Sec.
+ * 2.3.3): from the DoFs at the time of level first + n_int back to the time
+ * of level `first`, with `substeps` RK sub-steps per step; the velocity is
+ * linear in time between consecutive levels.  The scalar set by
+ * mmoc_set_scalar is the field at the time of level `first`.  Levels
+ * first .. first + n_int must be set.  Outputs as in mmoc_trace_step.  With
+ * a stationary velocity (first must be 0) this is one trace of length
+ * n_int * dt.  mmoc_trace_step(dt, S) is mmoc_trace_span(0, 1, dt, S). */
+mmoc_status mmoc_trace_span(mmoc_ctx* ctx, int first, int n_int, double dt, int substeps, void* c_hat_dev,
+                            double* X_dev);
+
 /* Statistics accumulated since creation or the last reset; synchronises. */
 mmoc_status mmoc_get_stats(mmoc_ctx* ctx, mmoc_stats* out);
 mmoc_status mmoc_reset_stats(mmoc_ctx* ctx);
+
+/* ---------------- integrator and time step (Sec. 3.1, Alg. 1) ------------- */
+
+/* Selects a general explicit Runge-Kutta method for the trace (the paper
+ * uses the classical RK4 and notes that any explicit RK method applies,
+ * Sec. 3.1).  Host arrays: a [stages][stages] row-major (strictly lower
+ * triangular, else MMOC_E_ARG), b [stages], c [stages] with c[0] == 0.
+ * Sub-step j of S computes, backwards in time, y_i = Y - h sum_{l<i} a_il k_l,
+ * k_i = u~(y_i) at theta_i = 1 - (j + c_i)/S (eq. linear-interpolation), and
+ * Y <- Y - h sum_i b_i k_i.  1 <= stages <= 7; stages = 0 restores the
+ * built-in classical RK4 (the fastest path).  MMOC_FP64 and MMOC_FP32_FIELDS
+ * contexts only (MMOC_E_UNSUPPORTED for MMOC_FP32_MIXED). */
+mmoc_status mmoc_set_rk_tableau(mmoc_ctx* ctx, int stages, const double* a, const double* b, const double* c);
+
+/* CFL time step of Alg. 1: *tau = cfl * h_min / max_i |u_i|, with the
+ * maximum over the nodal values of velocity level `level` (0 or 1) and
+ * h_min the shortest micro edge of the refined mesh (in the computational
+ * domain).  *umax and *hmin (each may be NULL) receive the two factors;
+ * *tau is +inf for a zero field.  Synchronises the stream. */
+mmoc_status mmoc_cfl_time_step(mmoc_ctx* ctx, double cfl, int level, double* tau, double* umax, double* hmin);
 
 /* ---------------- benchmark measures and look-back (Sec. 2.3.3, 3.1) ------ */
 
@@ -256,7 +305,7 @@ mmoc_status mmoc_mlp_infer(mmoc_ctx* ctx, double t_np1, double dt, double* X_dev
  * every particle of a tile in which some checked residual
  * |Xhat - X_rk4|_inf exceeds tol/2 is re-traced by RK4 (fallback).
  * Then chat = c_h^n(X) as in mmoc_trace_step.  c_hat_dev: double* for
- * MMOC_FP64 contexts, float* for MMOC_FP32_MIXED.  step seeds the sample. */
+ * MMOC_FP64 contexts, float* otherwise.  step seeds the sample. */
 mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* ctx, double t_np1, double dt, int substeps,
                                       float check_fraction, double tol, int64_t step,
                                       void* c_hat_dev, double* X_dev);

@@ -43,9 +43,9 @@
  *     barycentrics, and the element's polynomial is evaluated at the
  *     unclamped point (extrapolation; exact for fields of degree <= 2);
  *   - stage times: theta = 1 - (j + a_s)/S for sub-step j and RK4 node a_s;
- *   - spherical shell: per-column radial blending
+ *   - spherical shell and annulus: per-column radial blending
  *     Phi(x) = x (n.x)/(c |x|), Phi^-1(z) = z c |z| / (n.z), with the plane
- *     n.x = c through the column's three unit directions.
+ *     (2D: line) n.x = c through the tips of the column's unit directions.
  */
 #include <math.h>
 #include <stdint.h>
@@ -58,6 +58,7 @@ enum { F_OUTSIDE = 1, F_MULTIHOP = 2, F_BRUTE = 4, F_NAN = 8 };
 
 typedef struct orc_mesh {
     int dim, level, n, m, nv, nm, blend;
+    int order;       /* 2: P2 (DoFs on the lattice of resolution m = 2n); 1: P1 (m = n) */
     double *vert;    /* nv*dim, computational-domain coordinates */
     int32_t *mv;     /* nm*(dim+1) global vertex ids */
     double *v0;      /* nm*dim */
@@ -99,20 +100,20 @@ static void phi_fwd(const orc_mesh *g, int M, const double *x, double *z)
 {
     if (!g->blend) { for (int i = 0; i < g->dim; ++i) z[i] = x[i]; return; }
     const double *n = g->pn + 3 * M;
-    double nx = n[0] * x[0] + n[1] * x[1] + n[2] * x[2];
-    double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    double f = nx / (g->pc[M] * r);
-    for (int i = 0; i < 3; ++i) z[i] = x[i] * f;
+    double nx = 0, r2 = 0;
+    for (int i = 0; i < g->dim; ++i) { nx += n[i] * x[i]; r2 += x[i] * x[i]; }
+    double f = nx / (g->pc[M] * sqrt(r2));
+    for (int i = 0; i < g->dim; ++i) z[i] = x[i] * f;
 }
 
 static void phi_inv(const orc_mesh *g, int M, const double *z, double *x)
 {
     if (!g->blend) { for (int i = 0; i < g->dim; ++i) x[i] = z[i]; return; }
     const double *n = g->pn + 3 * M;
-    double nz = n[0] * z[0] + n[1] * z[1] + n[2] * z[2];
-    double r = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
-    double f = g->pc[M] * r / nz;
-    for (int i = 0; i < 3; ++i) x[i] = z[i] * f;
+    double nz = 0, r2 = 0;
+    for (int i = 0; i < g->dim; ++i) { nz += n[i] * z[i]; r2 += z[i] * z[i]; }
+    double f = g->pc[M] * sqrt(r2) / nz;
+    for (int i = 0; i < g->dim; ++i) x[i] = z[i] * f;
 }
 
 /* ------------------------------------------------------------- hash table */
@@ -177,15 +178,17 @@ void orc_mesh_free(orc_mesh *g)
     free(g);
 }
 
-/* Returns NULL on invalid input (bad sizes, degenerate macro, non-manifold face). */
-orc_mesh *orc_mesh_new(int dim, int level, int nv, const double *vert, int nm,
-                       const int32_t *mv, int blend)
+/* Returns NULL on invalid input (bad sizes, degenerate macro, non-manifold
+ * face).  order 2: P2 elements (the default); order 1: P1 elements, whose
+ * DoFs are the micro vertices (the lattice of resolution m = n). */
+orc_mesh *orc_mesh_new_order(int dim, int level, int order, int nv, const double *vert, int nm,
+                             const int32_t *mv, int blend)
 {
     if (dim < 2 || dim > 3 || level < 0 || level > 10 || nv <= 0 || nm <= 0) return NULL;
-    if (blend && dim != 3) return NULL;
+    if (order != 1 && order != 2) return NULL;
     orc_mesh *g = calloc(1, sizeof *g);
     int d = dim, nvm = dim + 1;
-    g->dim = dim; g->level = level; g->n = 1 << level; g->m = 2 * g->n;
+    g->dim = dim; g->level = level; g->n = 1 << level; g->m = order * g->n; g->order = order;
     g->nv = nv; g->nm = nm; g->blend = blend;
     g->vert = malloc(sizeof(double) * nv * d);
     memcpy(g->vert, vert, sizeof(double) * nv * d);
@@ -231,30 +234,42 @@ orc_mesh *orc_mesh_new(int dim, int level, int nv, const double *vert, int nm,
         }
     }
 
-    /* shell column planes: the three distinct unit directions of the macro */
+    /* radial blending: the column of a macro is spanned by its d distinct
+     * unit directions (a shell prism in 3D, an annulus sector in 2D); its
+     * plane (line in 2D) n.x = c passes through their tips, n unit, c > 0 */
     if (blend) {
-        g->pn = malloc(sizeof(double) * nm * 3);
+        g->pn = calloc((size_t)nm * 3, sizeof(double));
         g->pc = malloc(sizeof(double) * nm);
         for (int M = 0; M < nm; ++M) {
-            double dirs[4][3];
+            double dirs[4][3] = {{0}};
             int nd = 0;
-            for (int a = 0; a < 4; ++a) {
-                const double *p = vert + (size_t)mv[M * 4 + a] * 3;
-                double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-                double q[3] = {p[0] / r, p[1] / r, p[2] / r};
+            for (int a = 0; a < nvm; ++a) {
+                const double *p = vert + (size_t)mv[M * nvm + a] * d;
+                double r2 = 0;
+                for (int i = 0; i < d; ++i) r2 += p[i] * p[i];
+                double q[3] = {0, 0, 0};
+                for (int i = 0; i < d; ++i) q[i] = p[i] / sqrt(r2);
                 int dup = 0;
                 for (int b = 0; b < nd; ++b) {
                     double e = fabs(q[0] - dirs[b][0]) + fabs(q[1] - dirs[b][1]) + fabs(q[2] - dirs[b][2]);
                     if (e < 1e-9) dup = 1;
                 }
-                if (!dup) { memcpy(dirs[nd], q, sizeof q); ++nd; }
+                if (!dup && nd < 4) { memcpy(dirs[nd], q, sizeof q); ++nd; }
             }
-            if (nd != 3) { orc_mesh_free(g); return NULL; }
-            double e1[3], e2[3], nn[3];
-            for (int i = 0; i < 3; ++i) { e1[i] = dirs[1][i] - dirs[0][i]; e2[i] = dirs[2][i] - dirs[0][i]; }
-            nn[0] = e1[1] * e2[2] - e1[2] * e2[1];
-            nn[1] = e1[2] * e2[0] - e1[0] * e2[2];
-            nn[2] = e1[0] * e2[1] - e1[1] * e2[0];
+            if (nd != d) { orc_mesh_free(g); return NULL; }
+            double nn[3];
+            if (d == 3) {
+                double e1[3], e2[3];
+                for (int i = 0; i < 3; ++i) { e1[i] = dirs[1][i] - dirs[0][i]; e2[i] = dirs[2][i] - dirs[0][i]; }
+                nn[0] = e1[1] * e2[2] - e1[2] * e2[1];
+                nn[1] = e1[2] * e2[0] - e1[0] * e2[2];
+                nn[2] = e1[0] * e2[1] - e1[1] * e2[0];
+            } else {
+                /* normal of the chord between the two directions */
+                nn[0] = -(dirs[1][1] - dirs[0][1]);
+                nn[1] = dirs[1][0] - dirs[0][0];
+                nn[2] = 0;
+            }
             double ln = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
             double c = (nn[0] * dirs[0][0] + nn[1] * dirs[0][1] + nn[2] * dirs[0][2]) / ln;
             double sgn = c < 0 ? -1.0 : 1.0;
@@ -361,6 +376,11 @@ orc_mesh *orc_mesh_new(int dim, int level, int nv, const double *vert, int nm,
     g->own = realloc(own, sizeof(int32_t) * N);
     g->olat = realloc(olat, sizeof(int32_t) * N * 3);
     return g;
+}
+
+orc_mesh *orc_mesh_new(int dim, int level, int nv, const double *vert, int nm, const int32_t *mv, int blend)
+{
+    return orc_mesh_new_order(dim, level, 2, nv, vert, nm, mv, blend);
 }
 
 int64_t orc_num_dofs(const orc_mesh *g) { return g->N; }
@@ -539,8 +559,20 @@ static void micro_locate(const orc_mesh *g, int M, const double *y, orc_loc *L)
     L->mu[0] = 1.0 - fu[pi[0]];
     for (int a = 1; a < d; ++a) L->mu[a] = fu[pi[a - 1]] - fu[pi[a]];
     L->mu[d] = fu[pi[d - 1]];
-    /* P2 nodes: 2 V_a (vertices) and V_a + V_b (edge midpoints), m-lattice */
     int c = 0;
+    if (g->order == 1) {
+        /* P1: the vertices V_a themselves (m = n), shape functions mu_a */
+        for (int a = 0; a <= d; ++a) {
+            int P[3] = {0, 0, 0};
+            for (int i = 0; i < d; ++i) P[i] = L->V[a][i];
+            L->slot[c] = lat_idx(d, P[0], P[1], P[2]);
+            L->phi[c] = L->mu[a];
+            ++c;
+        }
+        L->nn = c;
+        return;
+    }
+    /* P2 nodes: 2 V_a (vertices) and V_a + V_b (edge midpoints), m-lattice */
     for (int a = 0; a <= d; ++a) {
         int P[3] = {0, 0, 0};
         for (int i = 0; i < d; ++i) P[i] = 2 * L->V[a][i];
@@ -663,6 +695,147 @@ int orc_trace(const orc_mesh *g, const double *u0, const double *u1, const doubl
     return 0;
 }
 
+/* ------------------------------------------- traces across steps, general RK */
+
+/* A trace across several time steps (look-back b > 1 with a time-dependent
+ * velocity, Sec. 2.3.3): the velocity is known at the levels t_l = t_0 + l
+ * tau, l = 0..n_int (U[l], each [dim][N]), and is linear in time on every
+ * interval [t_l, t_{l+1}] (eq. linear-interpolation, interval by interval).
+ * A particle at its DoF at t_{n_int} is traced back to t_0 with S classical
+ * RK4 sub-steps per interval (h = tau/S), and c (known at t_0) is evaluated
+ * at the departure point.  The stage of sub-step jj (0 at the latest time)
+ * with RK4 node a_s sits p = (jj + a_s)/S intervals before t_{n_int}; it lies
+ * in interval q = min(floor(p), n_int - 1) counted from the end, at weight
+ * theta = 1 - (p - q) of that interval's later level. */
+int orc_trace_span(const orc_mesh *g, const double *const *U, int n_int, const double *c, double tau, int S,
+                   int max_hops, int64_t n_ids, const int64_t *ids, double *chat, double *X, int64_t *stats)
+{
+    if (!(tau > 0) || S < 1 || n_int < 1) return -1;
+    int d = g->dim;
+    double h = tau / S;
+    static const double a_s[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int64_t q = 0; q < n_ids; ++q) {
+        int64_t i = ids ? ids[q] : q;
+        int M = g->own[i];
+        int flags = 0;
+        double Y[3], y[3], k[4][3];
+        node_pos(g, M, g->olat[3 * i], g->olat[3 * i + 1], g->olat[3 * i + 2], Y);
+        for (int jj = 0; jj < n_int * S; ++jj) {
+            for (int st = 0; st < 4; ++st) {
+                for (int x = 0; x < d; ++x) {
+                    if (st == 0) y[x] = Y[x];
+                    else if (st == 3) y[x] = Y[x] - h * k[2][x];
+                    else y[x] = Y[x] - 0.5 * h * k[st - 1][x];
+                }
+                double pos = (jj + a_s[st]) / S;
+                int iv = (int)floor(pos);
+                if (iv > n_int - 1) iv = n_int - 1;
+                double theta = 1.0 - (pos - iv);
+                const double *late = U[n_int - iv], *early = U[n_int - iv - 1];
+                M = orc_walk(g, M, y, max_hops, &flags);
+                orc_loc L;
+                micro_locate(g, M, y, &L);
+                for (int x = 0; x < d; ++x) {
+                    double ua = eval_loc(g, M, &L, early + (size_t)x * g->N);
+                    double ub = eval_loc(g, M, &L, late + (size_t)x * g->N);
+                    k[st][x] = (1.0 - theta) * ua + theta * ub;
+                }
+            }
+            for (int x = 0; x < d; ++x)
+                Y[x] = Y[x] - h / 6.0 * (k[0][x] + 2.0 * k[1][x] + 2.0 * k[2][x] + k[3][x]);
+        }
+        M = orc_walk(g, M, Y, max_hops, &flags);
+        orc_loc L;
+        micro_locate(g, M, Y, &L);
+        double v = eval_loc(g, M, &L, c);
+        chat[q] = v;
+        int bad = v != v;
+        for (int x = 0; x < d; ++x) {
+            if (X) X[(size_t)x * n_ids + q] = Y[x];
+            if (Y[x] != Y[x]) bad = 1;
+        }
+        if (bad) flags |= F_NAN;
+        if (stats) {
+            if (flags & F_OUTSIDE) stats[0]++;
+            if (flags & F_MULTIHOP) stats[1]++;
+            if (flags & F_BRUTE) stats[2]++;
+            if (flags & F_NAN) stats[3]++;
+        }
+    }
+    return 0;
+}
+
+/* One advection step with a general explicit Runge-Kutta method (the paper
+ * uses RK4 and notes that any explicit RK method applies, Sec. 3.1; Fig. 2
+ * shows a two-stage one).  Butcher tableau of ns stages: A [ns][ns]
+ * row-major (only the strictly lower part is read), weights b [ns], nodes
+ * cn [ns].  Backwards in time, sub-step j of S (h = dt/S):
+ *   y_i = Y - h sum_{l<i} A[i][l] k_l,   k_i = u~(y_i; theta_i),
+ *   theta_i = 1 - (j + cn[i])/S,         Y <- Y - h sum_i b[i] k_i,
+ * with u~ the linear-in-time velocity of eq. linear-interpolation, and the
+ * field evaluation, walk and scalar step exactly as in orc_trace. */
+int orc_trace_rk(const orc_mesh *g, const double *u0, const double *u1, const double *c,
+                 double dt, int S, int ns, const double *A, const double *b, const double *cn,
+                 int max_hops, int64_t n_ids, const int64_t *ids,
+                 double *chat, double *X, int64_t *stats)
+{
+    if (!(dt > 0) || S < 1 || ns < 1 || ns > 16) return -1;
+    int d = g->dim;
+    double h = dt / S;
+    for (int64_t q = 0; q < n_ids; ++q) {
+        int64_t i = ids ? ids[q] : q;
+        int M = g->own[i];
+        int flags = 0;
+        double Y[3], y[3], k[16][3];
+        node_pos(g, M, g->olat[3 * i], g->olat[3 * i + 1], g->olat[3 * i + 2], Y);
+        for (int j = 0; j < S; ++j) {
+            for (int st = 0; st < ns; ++st) {
+                for (int x = 0; x < d; ++x) {
+                    double sum = 0.0;
+                    for (int l = 0; l < st; ++l) sum += A[st * ns + l] * k[l][x];
+                    y[x] = Y[x] - h * sum;
+                }
+                double theta = 1.0 - (j + cn[st]) / S;
+                M = orc_walk(g, M, y, max_hops, &flags);
+                orc_loc L;
+                micro_locate(g, M, y, &L);
+                for (int x = 0; x < d; ++x) {
+                    double ua = eval_loc(g, M, &L, u0 + (size_t)x * g->N);
+                    if (u1) {
+                        double ub = eval_loc(g, M, &L, u1 + (size_t)x * g->N);
+                        k[st][x] = (1.0 - theta) * ua + theta * ub;
+                    } else {
+                        k[st][x] = ua;
+                    }
+                }
+            }
+            for (int x = 0; x < d; ++x) {
+                double sum = 0.0;
+                for (int st = 0; st < ns; ++st) sum += b[st] * k[st][x];
+                Y[x] = Y[x] - h * sum;
+            }
+        }
+        M = orc_walk(g, M, Y, max_hops, &flags);
+        orc_loc L;
+        micro_locate(g, M, Y, &L);
+        double v = eval_loc(g, M, &L, c);
+        chat[q] = v;
+        int bad = v != v;
+        for (int x = 0; x < d; ++x) {
+            if (X) X[(size_t)x * n_ids + q] = Y[x];
+            if (Y[x] != Y[x]) bad = 1;
+        }
+        if (bad) flags |= F_NAN;
+        if (stats) {
+            if (flags & F_OUTSIDE) stats[0]++;
+            if (flags & F_MULTIHOP) stats[1]++;
+            if (flags & F_BRUTE) stats[2]++;
+            if (flags & F_NAN) stats[3]++;
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------- P2 mass matrix */
 
 /* Integral over a simplex T of prod_a lambda_a^e_a equals
@@ -748,13 +921,28 @@ int64_t orc_micro_simplices(const orc_mesh *g, int32_t *V, int64_t cap)
     return cnt;
 }
 
-/* a^T M b for the P2 mass matrix M on the (unblended) mesh; a, b unique [N] */
+/* P1 reference mass matrix divided by |T|: int lambda_a lambda_b
+ * = |T| d! (1 + [a == b]) / (d + 2)! by the monomial formula */
+static void p1_mass_ref(int d, double *Mref)
+{
+    for (int a = 0; a <= d; ++a)
+        for (int b = 0; b <= d; ++b) {
+            int e[4] = {0, 0, 0, 0};
+            e[a] += 1;
+            e[b] += 1;
+            Mref[a * (d + 1) + b] = mono_int(d, e);
+        }
+}
+
+/* a^T M b for the mass matrix M of the mesh's elements (P2, or P1 for an
+ * order-1 mesh) on the (unblended) mesh; a, b unique [N] */
 double orc_mass_quadform(const orc_mesh *g, const double *a, const double *b)
 {
     int d = g->dim;
-    int nb = (d + 1) * (d + 2) / 2;
+    int nb = g->order == 1 ? d + 1 : (d + 1) * (d + 2) / 2;
     double Mref[100];
-    orc_p2_mass_ref(d, Mref);
+    if (g->order == 1) p1_mass_ref(d, Mref);
+    else orc_p2_mass_ref(d, Mref);
     int64_t nsimp = orc_micro_simplices(g, NULL, 0);
     int32_t *V = malloc(sizeof(int32_t) * 12 * nsimp);
     orc_micro_simplices(g, V, nsimp);
@@ -769,10 +957,15 @@ double orc_mass_quadform(const orc_mesh *g, const double *a, const double *b)
             int32_t (*vv)[3] = (int32_t (*)[3])(V + s * 12);
             int64_t nodes[10];
             int c = 0;
-            for (int x = 0; x <= d; ++x) nodes[c++] = lat_idx(d, 2 * vv[x][0], 2 * vv[x][1], d == 3 ? 2 * vv[x][2] : 0);
-            for (int x = 0; x <= d; ++x)
-                for (int y = x + 1; y <= d; ++y)
-                    nodes[c++] = lat_idx(d, vv[x][0] + vv[y][0], vv[x][1] + vv[y][1], d == 3 ? vv[x][2] + vv[y][2] : 0);
+            if (g->order == 1) {
+                for (int x = 0; x <= d; ++x) nodes[c++] = lat_idx(d, vv[x][0], vv[x][1], d == 3 ? vv[x][2] : 0);
+            } else {
+                for (int x = 0; x <= d; ++x)
+                    nodes[c++] = lat_idx(d, 2 * vv[x][0], 2 * vv[x][1], d == 3 ? 2 * vv[x][2] : 0);
+                for (int x = 0; x <= d; ++x)
+                    for (int y = x + 1; y <= d; ++y)
+                        nodes[c++] = lat_idx(d, vv[x][0] + vv[y][0], vv[x][1] + vv[y][1], d == 3 ? vv[x][2] + vv[y][2] : 0);
+            }
             double acc = 0;
             for (int i = 0; i < nb; ++i) {
                 double ai = a[g->uid[M * g->npm + nodes[i]]];
@@ -783,4 +976,210 @@ double orc_mass_quadform(const orc_mesh *g, const double *a, const double *b)
     }
     free(V);
     return total;
+}
+
+/* ------------------------------------------- Galerkin mass and stiffness
+ * The matrices M and A of the linear system of the Theta-method (Sec. 2.2,
+ * eq. linear-system): M_ij = (phi_j, phi_i), A_ij = (grad phi_j, grad phi_i)
+ * over the physical domain Phi(Omega_comp).  On a blended mesh the element
+ * map is Phi composed with the affine micro-simplex map, whose Jacobian is
+ * not constant; both integrals are then taken with a quadrature rule on the
+ * reference simplex that the caller passes in (points qp [nq][d] in
+ * reference coordinates, weights qw [nq] summing to the reference volume
+ * 1/d!).  Without blending the integrands are polynomials and a rule exact
+ * to degree 2*order makes the matrices exact. */
+
+/* Shape functions and their reference gradients at reference point xi:
+ * lambda_0 = 1 - sum xi, lambda_a = xi_a; P1: phi_a = lambda_a; P2: the
+ * vertex functions lambda_a (2 lambda_a - 1) for a = 0..d, then the edge
+ * functions 4 lambda_a lambda_b for a < b in lexicographic order. */
+static int shape_fn(int d, int order, const double *xi, double *phi, double dphi[10][3])
+{
+    double lam[4], dl[4][3];
+    memset(dl, 0, sizeof dl);
+    lam[0] = 1.0;
+    for (int a = 0; a < d; ++a) {
+        lam[0] -= xi[a];
+        lam[a + 1] = xi[a];
+        dl[0][a] = -1.0;
+        dl[a + 1][a] = 1.0;
+    }
+    int c = 0;
+    if (order == 1) {
+        for (int a = 0; a <= d; ++a, ++c) {
+            phi[c] = lam[a];
+            for (int i = 0; i < d; ++i) dphi[c][i] = dl[a][i];
+        }
+        return c;
+    }
+    for (int a = 0; a <= d; ++a, ++c) {
+        phi[c] = lam[a] * (2.0 * lam[a] - 1.0);
+        for (int i = 0; i < d; ++i) dphi[c][i] = (4.0 * lam[a] - 1.0) * dl[a][i];
+    }
+    for (int a = 0; a <= d; ++a)
+        for (int b = a + 1; b <= d; ++b, ++c) {
+            phi[c] = 4.0 * lam[a] * lam[b];
+            for (int i = 0; i < d; ++i) dphi[c][i] = 4.0 * (lam[b] * dl[a][i] + lam[a] * dl[b][i]);
+        }
+    return c;
+}
+
+/* D Phi at computational point x of macro M (row-major d x d):
+ * Phi(x) = f(x) x, f = (n.x)/(c |x|), so DPhi = f I + x (grad f)^T with
+ * grad f = n/(c |x|) - (n.x) x/(c |x|^3).  The identity without blending. */
+static void phi_jacobian(const orc_mesh *g, int M, const double *x, double *D)
+{
+    int d = g->dim;
+    for (int i = 0; i < d * d; ++i) D[i] = 0.0;
+    if (!g->blend) {
+        for (int i = 0; i < d; ++i) D[i * d + i] = 1.0;
+        return;
+    }
+    const double *n = g->pn + 3 * M;
+    double c = g->pc[M], nx = 0, r2 = 0;
+    for (int i = 0; i < d; ++i) { nx += n[i] * x[i]; r2 += x[i] * x[i]; }
+    double r = sqrt(r2), f = nx / (c * r), gf[3];
+    for (int i = 0; i < d; ++i) gf[i] = n[i] / (c * r) - nx * x[i] / (c * r * r2);
+    for (int i = 0; i < d; ++i) {
+        for (int j = 0; j < d; ++j) D[i * d + j] = x[i] * gf[j];
+        D[i * d + i] += f;
+    }
+}
+
+static double det_inv(int d, const double *J, double *Ji)
+{
+    if (d == 2) {
+        double det = J[0] * J[3] - J[1] * J[2];
+        Ji[0] = J[3] / det; Ji[1] = -J[1] / det; Ji[2] = -J[2] / det; Ji[3] = J[0] / det;
+        return det;
+    }
+    double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+    double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+    Ji[0] = c00 / det;
+    Ji[1] = (J[2] * J[7] - J[1] * J[8]) / det;
+    Ji[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+    Ji[3] = c01 / det;
+    Ji[4] = (J[0] * J[8] - J[2] * J[6]) / det;
+    Ji[5] = (J[2] * J[3] - J[0] * J[5]) / det;
+    Ji[6] = c02 / det;
+    Ji[7] = (J[1] * J[6] - J[0] * J[7]) / det;
+    Ji[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+    return det;
+}
+
+/* computational position of n-lattice vertex (I,J,K) of macro M */
+static void nlat_pos(const orc_mesh *g, int M, const int32_t *v, double *x)
+{
+    int d = g->dim;
+    double s[3];
+    if (d == 2) { s[0] = (double)(v[0] - v[1]) / g->n; s[1] = (double)v[1] / g->n; }
+    else { s[0] = (double)(v[0] - v[1]) / g->n; s[1] = (double)(v[1] - v[2]) / g->n; s[2] = (double)v[2] / g->n; }
+    const double *v0 = g->v0 + (size_t)M * d, *B = g->B + (size_t)M * d * d;
+    for (int i = 0; i < d; ++i) {
+        double acc = v0[i];
+        for (int a = 0; a < d; ++a) acc = acc + B[i * d + a] * s[a];
+        x[i] = acc;
+    }
+}
+
+/* Element matrices of every micro simplex as triplets (row, col, m, a):
+ * for each macro, each micro simplex (in orc_micro_simplices order), each
+ * local pair (i, j):
+ *   m = sum_q w_q phi_i(xi_q) phi_j(xi_q) |det J(xi_q)|,
+ *   a = sum_q w_q (J^-T grad phi_i).(J^-T grad phi_j) |det J(xi_q)|,
+ * J(xi) = DPhi(x(xi)) [p_1 - p_0, ..., p_d - p_0], x(xi) = p_0 + sum_a
+ * xi_a (p_a - p_0) with p_a the simplex's computational vertices.  Rows and
+ * columns are unique DoF ids.  Returns the triplet count (written only when
+ * it fits cap). */
+int64_t orc_assemble(const orc_mesh *g, int nq, const double *qp, const double *qw, int64_t cap, int64_t *rows,
+                     int64_t *cols, double *mvals, double *avals)
+{
+    int d = g->dim;
+    int nb = g->order == 1 ? d + 1 : (d + 1) * (d + 2) / 2;
+    int64_t nsimp = orc_micro_simplices(g, NULL, 0);
+    int64_t total = (int64_t)g->nm * nsimp * nb * nb;
+    if (!rows || total > cap) return total;
+    int32_t *V = malloc(sizeof(int32_t) * 12 * nsimp);
+    orc_micro_simplices(g, V, nsimp);
+    int64_t t = 0;
+    for (int M = 0; M < g->nm; ++M)
+        for (int64_t s = 0; s < nsimp; ++s) {
+            int32_t (*vv)[3] = (int32_t (*)[3])(V + s * 12);
+            int64_t nodes[10];
+            int c = 0;
+            if (g->order == 1) {
+                for (int x = 0; x <= d; ++x) nodes[c++] = lat_idx(d, vv[x][0], vv[x][1], d == 3 ? vv[x][2] : 0);
+            } else {
+                for (int x = 0; x <= d; ++x)
+                    nodes[c++] = lat_idx(d, 2 * vv[x][0], 2 * vv[x][1], d == 3 ? 2 * vv[x][2] : 0);
+                for (int x = 0; x <= d; ++x)
+                    for (int y = x + 1; y <= d; ++y)
+                        nodes[c++] = lat_idx(d, vv[x][0] + vv[y][0], vv[x][1] + vv[y][1],
+                                             d == 3 ? vv[x][2] + vv[y][2] : 0);
+            }
+            double p[4][3], E[9];
+            for (int a = 0; a <= d; ++a) nlat_pos(g, M, vv[a], p[a]);
+            for (int i = 0; i < d; ++i)
+                for (int a = 0; a < d; ++a) E[i * d + a] = p[a + 1][i] - p[0][i];
+            double me[100] = {0}, ae[100] = {0};
+            for (int q = 0; q < nq; ++q) {
+                const double *xi = qp + (size_t)q * d;
+                double x[3], D[9], J[9] = {0}, Ji[9], phi[10], dphi[10][3], gp[10][3];
+                for (int i = 0; i < d; ++i) {
+                    x[i] = p[0][i];
+                    for (int a = 0; a < d; ++a) x[i] += xi[a] * E[i * d + a];
+                }
+                phi_jacobian(g, M, x, D);
+                for (int i = 0; i < d; ++i)
+                    for (int j = 0; j < d; ++j) {
+                        double acc = 0;
+                        for (int k = 0; k < d; ++k) acc += D[i * d + k] * E[k * d + j];
+                        J[i * d + j] = acc;
+                    }
+                double wdet = qw[q] * fabs(det_inv(d, J, Ji));
+                shape_fn(d, g->order, xi, phi, dphi);
+                /* physical gradient: grad phi = J^-T grad_xi phi */
+                for (int b = 0; b < nb; ++b)
+                    for (int i = 0; i < d; ++i) {
+                        double acc = 0;
+                        for (int k = 0; k < d; ++k) acc += Ji[k * d + i] * dphi[b][k];
+                        gp[b][i] = acc;
+                    }
+                for (int i = 0; i < nb; ++i)
+                    for (int j = 0; j < nb; ++j) {
+                        double dot = 0;
+                        for (int k = 0; k < d; ++k) dot += gp[i][k] * gp[j][k];
+                        me[i * nb + j] += wdet * phi[i] * phi[j];
+                        ae[i * nb + j] += wdet * dot;
+                    }
+            }
+            for (int i = 0; i < nb; ++i)
+                for (int j = 0; j < nb; ++j, ++t) {
+                    rows[t] = g->uid[(size_t)M * g->npm + nodes[i]];
+                    cols[t] = g->uid[(size_t)M * g->npm + nodes[j]];
+                    mvals[t] = me[i * nb + j];
+                    avals[t] = ae[i * nb + j];
+                }
+        }
+    free(V);
+    return t;
+}
+
+/* mask[u] = 1 for DoFs on the domain boundary: lattice nodes of a macro face
+ * that has no neighbouring macro (barycentric weight of the opposite vertex
+ * zero); 0 elsewhere. */
+void orc_boundary_mask(const orc_mesh *g, uint8_t *mask)
+{
+    int d = g->dim, m = g->m;
+    memset(mask, 0, (size_t)g->N);
+    for (int M = 0; M < g->nm; ++M)
+        for (int I = 0; I <= m; ++I)
+            for (int J = 0; J <= I; ++J)
+                for (int K = 0; K <= (d == 3 ? J : 0); ++K) {
+                    int w[4];
+                    lat_weights(d, m, I, J, K, w);
+                    for (int k = 0; k <= d; ++k)
+                        if (w[k] == 0 && g->nbr[M * (d + 1) + k] < 0)
+                            mask[g->uid[(size_t)M * g->npm + lat_idx(d, I, J, K)]] = 1;
+                }
 }

@@ -50,6 +50,8 @@ def lib():
             lp = C.POINTER(C.c_int64)
             L.orc_mesh_new.restype = P
             L.orc_mesh_new.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_int, ip, C.c_int]
+            L.orc_mesh_new_order.restype = P
+            L.orc_mesh_new_order.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_int, ip, C.c_int]
             L.orc_mesh_free.argtypes = [P]
             L.orc_num_dofs.restype = C.c_int64
             L.orc_num_dofs.argtypes = [P]
@@ -72,11 +74,20 @@ def lib():
             L.orc_trace.restype = C.c_int
             L.orc_trace.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_int64, lp,
                                     dp, dp, lp]
+            L.orc_trace_rk.restype = C.c_int
+            L.orc_trace_rk.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_int, dp, dp, dp, C.c_int,
+                                       C.c_int64, lp, dp, dp, lp]
+            L.orc_trace_span.restype = C.c_int
+            L.orc_trace_span.argtypes = [P, C.POINTER(dp), C.c_int, dp, C.c_double, C.c_int, C.c_int, C.c_int64,
+                                         lp, dp, dp, lp]
             L.orc_p2_mass_ref.argtypes = [C.c_int, dp]
             L.orc_micro_simplices.restype = C.c_int64
             L.orc_micro_simplices.argtypes = [P, ip, C.c_int64]
             L.orc_mass_quadform.restype = C.c_double
             L.orc_mass_quadform.argtypes = [P, dp, dp]
+            L.orc_assemble.restype = C.c_int64
+            L.orc_assemble.argtypes = [P, C.c_int, dp, dp, C.c_int64, lp, lp, dp, dp]
+            L.orc_boundary_mask.argtypes = [P, C.POINTER(C.c_uint8)]
             if hasattr(L, "orc_mlp_forward"):
                 _bind_mlp(L)
             _lib = L
@@ -112,17 +123,18 @@ def _lp(a):
 
 
 class Mesh:
-    """Oracle view of a macro mesh refined to ``level``."""
+    """Oracle view of a macro mesh refined to ``level``, with P2 (order 2)
+    or P1 (order 1) elements."""
 
-    def __init__(self, dim, level, vertices, macros, blend=0):
+    def __init__(self, dim, level, vertices, macros, blend=0, order=2):
         L = lib()
-        self.dim, self.level, self.blend = int(dim), int(level), int(blend)
+        self.dim, self.level, self.blend, self.order = int(dim), int(level), int(blend), int(order)
         self.n = 1 << self.level
-        self.m = 2 * self.n
+        self.m = self.order * self.n
         self.vertices = np.ascontiguousarray(vertices, dtype=np.float64)
         self.macros = np.ascontiguousarray(macros, dtype=np.int32)
-        self._h = L.orc_mesh_new(self.dim, self.level, self.vertices.shape[0], _dp(self.vertices),
-                                 self.macros.shape[0], _ip(self.macros), self.blend)
+        self._h = L.orc_mesh_new_order(self.dim, self.level, self.order, self.vertices.shape[0],
+                                       _dp(self.vertices), self.macros.shape[0], _ip(self.macros), self.blend)
         if not self._h:
             raise ValueError("oracle rejected the mesh")
         self.N = int(L.orc_num_dofs(self._h))
@@ -130,8 +142,8 @@ class Mesh:
         self.nm = int(self.macros.shape[0])
 
     @classmethod
-    def from_workload(cls, wl, level=None):
-        return cls(wl.dim, wl.level if level is None else level, wl.vertices, wl.macros, wl.blend)
+    def from_workload(cls, wl, level=None, order=2):
+        return cls(wl.dim, wl.level if level is None else level, wl.vertices, wl.macros, wl.blend, order)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -216,8 +228,10 @@ class Mesh:
                        int(max_hops), _dp(out), _ip(mac), _ip(fl))
         return out, mac, fl
 
-    def trace(self, u0, u1, c, dt, substeps, ids=None, max_hops=64, threads=1):
-        """One advection step; returns (chat [n], X [dim][n], stats [4])."""
+    def trace(self, u0, u1, c, dt, substeps, ids=None, max_hops=64, threads=1, tableau=None):
+        """One advection step; returns (chat [n], X [dim][n], stats [4]).
+        tableau = (A [s][s], b [s], c [s]) selects a general explicit RK
+        method (orc_trace_rk); None is the classical RK4 (orc_trace)."""
         u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(self.dim, self.N)
         u1 = None if u1 is None else np.ascontiguousarray(u1, dtype=np.float64).reshape(self.dim, self.N)
         c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.N)
@@ -230,16 +244,67 @@ class Mesh:
         X = np.empty((self.dim, n))
         stats = np.zeros(4, dtype=np.int64)
         L = lib()
+        if tableau is not None:
+            tA = np.ascontiguousarray(tableau[0], dtype=np.float64)
+            tb = np.ascontiguousarray(tableau[1], dtype=np.float64)
+            tc = np.ascontiguousarray(tableau[2], dtype=np.float64)
+            ns = tb.shape[0]
+            assert tA.shape == (ns, ns) and tc.shape == (ns,)
 
         def run(lo, hi, st):
             sub_ids = np.ascontiguousarray(ids_arr[lo:hi])
             ch = np.empty(hi - lo)
             Xs = np.empty((self.dim, hi - lo))
-            r = L.orc_trace(self._h, _dp(u0), _dp(u1) if u1 is not None else None, _dp(c),
-                            float(dt), int(substeps), int(max_hops), hi - lo, _lp(sub_ids),
-                            _dp(ch), _dp(Xs), _lp(st))
+            if tableau is None:
+                r = L.orc_trace(self._h, _dp(u0), _dp(u1) if u1 is not None else None, _dp(c),
+                                float(dt), int(substeps), int(max_hops), hi - lo, _lp(sub_ids),
+                                _dp(ch), _dp(Xs), _lp(st))
+            else:
+                r = L.orc_trace_rk(self._h, _dp(u0), _dp(u1) if u1 is not None else None, _dp(c),
+                                   float(dt), int(substeps), ns, _dp(tA), _dp(tb), _dp(tc), int(max_hops),
+                                   hi - lo, _lp(sub_ids), _dp(ch), _dp(Xs), _lp(st))
             if r != 0:
                 raise ValueError("oracle trace rejected its arguments")
+            chat[lo:hi] = ch
+            X[:, lo:hi] = Xs
+
+        if threads <= 1 or n < 2 * threads:
+            run(0, n, stats)
+        else:
+            bounds = np.linspace(0, n, threads + 1).astype(np.int64)
+            sts = [np.zeros(4, dtype=np.int64) for _ in range(threads)]
+            ths = [threading.Thread(target=run, args=(int(bounds[k]), int(bounds[k + 1]), sts[k]))
+                   for k in range(threads)]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+            stats = sum(sts)
+        return chat, X, stats
+
+    def trace_span(self, levels, c, tau, substeps, ids=None, max_hops=64, threads=1):
+        """Trace across len(levels) - 1 time steps of length tau: levels[l] is
+        the velocity ([dim][N]) at t_0 + l tau, linear in time on each step;
+        RK4 with `substeps` sub-steps per step; c is known at t_0.  Returns
+        (chat [n], X [dim][n], stats [4])."""
+        Us = [np.ascontiguousarray(u, dtype=np.float64).reshape(self.dim, self.N) for u in levels]
+        n_int = len(Us) - 1
+        arr = (C.POINTER(C.c_double) * len(Us))(*[_dp(u) for u in Us])
+        c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.N)
+        ids_arr = np.arange(self.N, dtype=np.int64) if ids is None else np.ascontiguousarray(ids, dtype=np.int64)
+        n = ids_arr.shape[0]
+        chat = np.empty(n)
+        X = np.empty((self.dim, n))
+        stats = np.zeros(4, dtype=np.int64)
+        L = lib()
+
+        def run(lo, hi, st):
+            sub = np.ascontiguousarray(ids_arr[lo:hi])
+            ch = np.empty(hi - lo)
+            Xs = np.empty((self.dim, hi - lo))
+            if L.orc_trace_span(self._h, arr, n_int, _dp(c), float(tau), int(substeps), int(max_hops), hi - lo,
+                                _lp(sub), _dp(ch), _dp(Xs), _lp(st)) != 0:
+                raise ValueError("oracle trace_span rejected its arguments")
             chat[lo:hi] = ch
             X[:, lo:hi] = Xs
 
@@ -261,6 +326,87 @@ class Mesh:
         a = np.ascontiguousarray(a, dtype=np.float64)
         b = np.ascontiguousarray(b, dtype=np.float64)
         return float(lib().orc_mass_quadform(self._h, _dp(a), _dp(b)))
+
+
+    # ------------------------------------------------ diffusion (Sec. 2.2)
+
+    def assemble(self, rule=None):
+        """Mass and stiffness matrices (scipy CSR, N x N) of the mesh's
+        elements, integrated with ``rule`` = (points [nq][d], weights [nq])
+        on the reference simplex; default: the collapsed Gauss rule with 4
+        points per direction (exact to degree 6 in 2D, 5 in 3D)."""
+        import scipy.sparse as sp
+        qp, qw = simplex_rule(self.dim, 4) if rule is None else rule
+        qp = np.ascontiguousarray(qp, dtype=np.float64)
+        qw = np.ascontiguousarray(qw, dtype=np.float64)
+        L = lib()
+        cnt = int(L.orc_assemble(self._h, qw.shape[0], _dp(qp), _dp(qw), 0, None, None, None, None))
+        rows = np.empty(cnt, dtype=np.int64)
+        cols = np.empty(cnt, dtype=np.int64)
+        mv = np.empty(cnt)
+        av = np.empty(cnt)
+        L.orc_assemble(self._h, qw.shape[0], _dp(qp), _dp(qw), cnt, _lp(rows), _lp(cols), _dp(mv), _dp(av))
+        Mm = sp.coo_matrix((mv, (rows, cols)), shape=(self.N, self.N)).tocsr()
+        Am = sp.coo_matrix((av, (rows, cols)), shape=(self.N, self.N)).tocsr()
+        return Mm, Am
+
+    def boundary_mask(self):
+        out = np.empty(self.N, dtype=np.uint8)
+        lib().orc_boundary_mask(self._h, out.ctypes.data_as(C.POINTER(C.c_uint8)))
+        return out.astype(bool)
+
+
+def simplex_rule(dim, n):
+    """Collapsed (conical product) Gauss rule on the reference simplex
+    {xi >= 0, sum xi <= 1}: Gauss-Legendre nodes u, v (, w) on [0, 1] mapped
+    by xi = (u, v (1 - u)) in 2D and (u, v (1 - u), w (1 - u)(1 - v)) in 3D,
+    the weights multiplied by the map's Jacobian (1 - u), resp.
+    (1 - u)^2 (1 - v).  The Jacobian raises the degree in u by dim - 1, so
+    the rule is exact for polynomials of total degree 2n - dim."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    g = (g + 1.0) / 2.0
+    w = w / 2.0
+    pts, wts = [], []
+    if dim == 2:
+        for i in range(n):
+            for j in range(n):
+                u, v = g[i], g[j]
+                pts.append((u, v * (1 - u)))
+                wts.append(w[i] * w[j] * (1 - u))
+    else:
+        for i in range(n):
+            for j in range(n):
+                for k in range(n):
+                    u, v, t = g[i], g[j], g[k]
+                    pts.append((u, v * (1 - u), t * (1 - u) * (1 - v)))
+                    wts.append(w[i] * w[j] * w[k] * (1 - u) ** 2 * (1 - v))
+    return np.array(pts), np.array(wts)
+
+
+def diffusion_solve(M, A, c_hat, tau, kappa, theta=1.0, q0=None, q1=None, mask=None, g=None):
+    """One diffusion step of the Theta-method (Sec. 2.2, eq. linear-system):
+    (M + tau Theta kappa A) c = (M - tau (1 - Theta) kappa A) c_hat
+                                + tau (Theta q1 + (1 - Theta) q0),
+    q0 / q1 the load vectors (q(t_n), v_i) and (q(t_{n+1}), v_i) (None:
+    zero).  Dirichlet DoFs (mask True) take the values g; their rows are the
+    identity and their known values move to the right-hand side of the other
+    rows.  Solved exactly by a sparse direct factorisation."""
+    import scipy.sparse.linalg as sla
+    N = M.shape[0]
+    E = (M + (tau * theta * kappa) * A).tocsr()
+    rhs = (M - (tau * (1.0 - theta) * kappa) * A) @ c_hat
+    if q0 is not None or q1 is not None:
+        q0 = np.zeros(N) if q0 is None else q0
+        q1 = np.zeros(N) if q1 is None else q1
+        rhs = rhs + tau * (theta * q1 + (1.0 - theta) * q0)
+    if mask is None or not mask.any():
+        return sla.spsolve(E.tocsc(), rhs)
+    free = ~mask
+    x = np.zeros(N)
+    x[mask] = g[mask]
+    rf = rhs[free] - E[free][:, mask] @ g[mask]
+    x[free] = sla.spsolve(E[free][:, free].tocsc(), rf)
+    return x
 
 
 def p2_mass_ref(dim):

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/mmoc.h"
 #include "mmoc_internal.h"
@@ -26,14 +27,21 @@ struct mmoc_ctx {
     mmoc::MacroGeo* geo_d = nullptr;
     uint64_t* owned_d = nullptr;     // unique order
     int32_t* slot_uid_d = nullptr;
-    void* va_d[2] = {nullptr, nullptr};  // per level: (u_x,u_y) pairs, or (u_x,u_y,u_z) triples (3D float32)
-    void* vb_d[2] = {nullptr, nullptr};  // per level: u_z (3D float64)
+    // velocity levels, a ring of lev_cap: logical level l (l = 0 the oldest
+    // time) lives in physical slot (rot + l) % lev_cap; slot q of va_all
+    // starts at element q * va_lstride
+    void* va_all = nullptr;  // (u_x,u_y) pairs, or (u_x,u_y,u_z) triples (3D float32)
+    void* vb_all = nullptr;  // u_z (3D float64)
+    int64_t va_lstride = 0, vb_lstride = 0;
+    int lev_cap = 2;
+    int rot = 0;
     void* cs_d = nullptr;                // scalar
-    int swap = 0;                        // array set holding t_n
-    bool vel_set[2] = {false, false};
+    std::vector<char> vel_set = std::vector<char>(2, 0);  // per logical level
     bool scalar_set = false;
     bool stationary = false;
     unsigned long long* stats_d = nullptr;
+    double hmin = 0.0;        // shortest micro edge (computational domain)
+    mmoc::RKTab rk{};         // general explicit RK tableau (s == 0: classical RK4)
     double* red_d = nullptr;  // partial sums of the metric reductions, red_cap doubles
     int64_t red_cap = 0;
 
@@ -48,8 +56,12 @@ mmoc_status check_dev(mmoc_ctx* c, const void* p, size_t bytes, size_t align, co
 mmoc_status mmoc_check_step_args(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X);
 // launches the RK4 tracer on the particles order[0..n) (order null: all, lane t
 // traces DoF t); n_dev (optional) is a device-side count that bounds the lanes
+// Each particle is traced from logical velocity level first + n_int back to
+// level first, n_int intervals of length dt with `substeps` RK sub-steps each.
 mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* order,
-                              int64_t n, const unsigned long long* n_dev = nullptr);
+                              int64_t n, const unsigned long long* n_dev = nullptr, int first = 0, int n_int = 1);
+// physical ring slot of logical velocity level l
+inline int phys_level(const mmoc_ctx* c, int l) { return (c->rot + l) % c->lev_cap; }
 void mmoc_mlp_free_state(mmoc_ctx* c);
 
 #define HIPCHK(ctx, call, what)                                \

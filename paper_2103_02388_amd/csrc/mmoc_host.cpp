@@ -94,6 +94,41 @@ mmoc_status dev_alloc(mmoc_ctx* c, T** p, size_t count, const char* what)
     return MMOC_OK;
 }
 
+mmoc_status alloc_clear(mmoc_ctx* c, void** p, size_t bytes, const char* what)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(c, e, what);
+    }
+    HIPCHK(c, hipMemsetAsync(*p, 0, bytes, c->stream), what);
+    return MMOC_OK;
+}
+
+// (Re)allocates the ring of `levels` velocity levels; every level unset.
+mmoc_status alloc_velocity_levels(mmoc_ctx* c, int levels)
+{
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->va_all);
+    (void)hipFree(c->vb_all);
+    c->va_all = c->vb_all = nullptr;
+    const bool f32 = c->prec != MMOC_FP64;
+    const size_t elem = f32 ? sizeof(float) : sizeof(double);
+    const int na = (c->dim == 3 && f32) ? 3 : 2;
+    c->va_lstride = c->nslots * na;
+    c->vb_lstride = (c->dim == 3 && !f32) ? c->nslots : 0;
+    mmoc_status st;
+    if ((st = alloc_clear(c, &c->va_all, (size_t)c->va_lstride * elem * levels, "velocity arrays")) != MMOC_OK)
+        return st;
+    if (c->vb_lstride &&
+        (st = alloc_clear(c, &c->vb_all, (size_t)c->vb_lstride * elem * levels, "velocity arrays")) != MMOC_OK)
+        return st;
+    c->lev_cap = levels;
+    c->rot = 0;
+    c->vel_set.assign(levels, 0);
+    return MMOC_OK;
+}
+
 int64_t lattice_count(int dim, int m)
 {
     return dim == 2 ? (int64_t)(m + 1) * (m + 2) / 2 : (int64_t)(m + 1) * (m + 2) * (m + 3) / 6;
@@ -146,6 +181,7 @@ void mmoc_default_options(mmoc_options* o)
     o->eps32_macro = 4e-6f;
     o->eps32_micro = 0.0f;  // micro ties are value-neutral (P2 is continuous across micro faces)
     o->max_hops = 64;
+    o->order = 2;
 }
 
 mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec, const mmoc_options* opt,
@@ -155,18 +191,20 @@ mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec,
     *out = nullptr;
     if (dim != 2 && dim != 3) return MMOC_E_ARG;
     if (level < 0 || level > 10 || (dim == 3 && level > 9)) return MMOC_E_ARG;  // lattice index fits int32
-    if (prec != MMOC_FP64 && prec != MMOC_FP32_MIXED) return MMOC_E_ARG;
-    if (opt && (!(opt->eps_in >= 0) || opt->max_hops < 0 || !(opt->eps32_macro >= 0) || !(opt->eps32_micro >= 0)))
+    if (prec != MMOC_FP64 && prec != MMOC_FP32_MIXED && prec != MMOC_FP32_FIELDS) return MMOC_E_ARG;
+    if (opt && (!(opt->eps_in >= 0) || opt->max_hops < 0 || !(opt->eps32_macro >= 0) || !(opt->eps32_micro >= 0) ||
+                opt->order < 0 || opt->order > 2))
         return MMOC_E_ARG;
     mmoc_ctx* c = new (std::nothrow) mmoc_ctx();
     if (!c) return MMOC_E_NOMEM;
     c->dim = dim;
     c->level = level;
     c->n = 1 << level;
-    c->m = 2 * c->n;
     c->prec = prec;
     if (opt) c->opt = *opt;
     else mmoc_default_options(&c->opt);
+    if (c->opt.order == 0) c->opt.order = 2;
+    c->m = c->opt.order * c->n;  // DoF lattice: 2n for P2, n for P1
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
         (void)hipGetLastError();
@@ -196,7 +234,8 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
     if (c->mesh_ok) return fail(c, MMOC_E_STATE, "mesh already uploaded");
     if (!vert || !mv || nv <= 0 || nm <= 0) return fail(c, MMOC_E_ARG, "empty mesh or null array");
     if (blend != MMOC_BLEND_NONE && blend != MMOC_BLEND_SHELL_RADIAL) return fail(c, MMOC_E_ARG, "unknown blend");
-    if (blend == MMOC_BLEND_SHELL_RADIAL && c->dim != 3) return fail(c, MMOC_E_UNSUPPORTED, "shell blending needs dim 3");
+    if (blend == MMOC_BLEND_SHELL_RADIAL && c->m != 2 * c->n)
+        return fail(c, MMOC_E_UNSUPPORTED, "P1 elements are not built for blended meshes");
     const int d = c->dim, nvm = d + 1;
     if (nm >= (1 << 27)) return fail(c, MMOC_E_ARG, "too many macros");
     const int64_t npm = lattice_count(d, c->m);
@@ -213,6 +252,7 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
 
     // --- geometry
     std::vector<MacroGeo> geo(nm);
+    double hmin = INFINITY;
     for (int M = 0; M < nm; ++M) {
         MacroGeo& G = geo[M];
         std::memset(&G, 0, sizeof G);
@@ -229,6 +269,33 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
         const double det = invert(d, B, Bi);
         if (!(std::fabs(det) > 1e-12 * std::pow(scale, d)))
             return fail(c, MMOC_E_MESH, "macro %d is degenerate (det %.3g)", M, det);
+        // shortest micro edge: the Kuhn lattice directions g_a = b_a - b_{a-1}
+        // (b_0 = 0, b_a the macro edge v_a - v0) and their sums over
+        // consecutive axes of some axis order, i.e. over every non-empty axis
+        // subset at level >= 1; at level 0 the micro element is the macro
+        {
+            double g[3][3] = {};
+            for (int a = 0; a < d; ++a)
+                for (int i = 0; i < d; ++i) g[a][i] = B[i * d + a] - (a > 0 ? B[i * d + a - 1] : 0.0);
+            for (int mask = 1; mask < (1 << d); ++mask) {
+                bool contiguous = true;  // axes a..b without a gap: an edge of the macro itself
+                int lo = -1, hi = -1;
+                for (int a = 0; a < d; ++a)
+                    if (mask & (1 << a)) {
+                        if (lo < 0) lo = a;
+                        hi = a;
+                    }
+                for (int a = lo; a <= hi; ++a) contiguous &= (mask >> a) & 1;
+                if (c->level == 0 && !contiguous) continue;
+                double v[3] = {};
+                for (int a = 0; a < d; ++a)
+                    if (mask & (1 << a))
+                        for (int i = 0; i < d; ++i) v[i] += g[a][i];
+                double len = 0.0;
+                for (int i = 0; i < d; ++i) len += v[i] * v[i];
+                hmin = std::min(hmin, std::sqrt(len) / c->n);
+            }
+        }
         for (int r = 0; r < d; ++r)
             for (int q = 0; q < d; ++q) {
                 G.B[r * 3 + q] = B[r * d + q];
@@ -236,32 +303,39 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
                 G.binvf[r * 3 + q] = (float)Bi[r * d + q];
             }
         if (blend == MMOC_BLEND_SHELL_RADIAL) {
-            // plane through the macro's three unit directions: n' with n'.d_k = 1
-            double dirs[3][3];
+            // plane (2D: line) through the tips of the macro's d unit
+            // directions: n' with n'.d_k = 1 for each direction d_k
+            double dirs[3][3] = {};
             int nd = 0;
-            for (int a = 0; a < 4; ++a) {
-                const double* p = vert + (size_t)mv[M * 4 + a] * 3;
-                const double r = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-                if (!(r > 0)) return fail(c, MMOC_E_MESH, "shell vertex at the origin");
-                const double q[3] = {p[0] / r, p[1] / r, p[2] / r};
+            for (int a = 0; a < nvm; ++a) {
+                const double* p = vert + (size_t)mv[M * nvm + a] * d;
+                double r2 = 0.0;
+                for (int i = 0; i < d; ++i) r2 += p[i] * p[i];
+                const double r = std::sqrt(r2);
+                if (!(r > 0)) return fail(c, MMOC_E_MESH, "blended mesh has a vertex at the origin");
+                double q[3] = {};
+                for (int i = 0; i < d; ++i) q[i] = p[i] / r;
                 bool dup = false;
                 for (int b = 0; b < nd; ++b)
                     dup |= std::fabs(q[0] - dirs[b][0]) + std::fabs(q[1] - dirs[b][1]) + std::fabs(q[2] - dirs[b][2]) < 1e-9;
                 if (!dup) {
-                    if (nd == 3) return fail(c, MMOC_E_MESH, "macro %d spans more than three radial directions", M);
+                    if (nd == d) return fail(c, MMOC_E_MESH, "macro %d spans more than %d radial directions", M, d);
                     std::memcpy(dirs[nd++], q, sizeof q);
                 }
             }
-            if (nd != 3) return fail(c, MMOC_E_MESH, "macro %d spans fewer than three radial directions", M);
+            if (nd != d) return fail(c, MMOC_E_MESH, "macro %d spans fewer than %d radial directions", M, d);
             double D[9], Di[9];
-            for (int r = 0; r < 3; ++r)
-                for (int q = 0; q < 3; ++q) D[r * 3 + q] = dirs[r][q];  // rows: directions
-            const double dd = invert(3, D, Di);
+            for (int r = 0; r < d; ++r)
+                for (int q = 0; q < d; ++q) D[r * d + q] = dirs[r][q];  // rows: directions
+            const double dd = invert(d, D, Di);
             if (!(std::fabs(dd) > 1e-14)) return fail(c, MMOC_E_MESH, "macro %d has a flat column", M);
-            double np[3];
-            for (int r = 0; r < 3; ++r) np[r] = Di[r * 3 + 0] + Di[r * 3 + 1] + Di[r * 3 + 2];  // D n' = 1
-            const double len = std::sqrt(np[0] * np[0] + np[1] * np[1] + np[2] * np[2]);
-            for (int r = 0; r < 3; ++r) G.pn[r] = np[r] / len;
+            double np[3] = {}, len2 = 0.0;
+            for (int r = 0; r < d; ++r) {
+                for (int q = 0; q < d; ++q) np[r] += Di[r * d + q];  // D n' = 1
+                len2 += np[r] * np[r];
+            }
+            const double len = std::sqrt(len2);
+            for (int r = 0; r < d; ++r) G.pn[r] = np[r] / len;
             G.pc = 1.0 / len;
         }
     }
@@ -370,6 +444,7 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
 
     // --- upload
     c->nm = nm;
+    c->hmin = hmin;
     c->npm = npm;
     c->nslots = (int64_t)nm * npm;
     c->N = N;
@@ -378,26 +453,13 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
     if ((st = dev_alloc(c, &c->geo_d, nm, "geometry")) != MMOC_OK) return st;
     if ((st = dev_alloc(c, &c->owned_d, (size_t)N, "particle table")) != MMOC_OK) return st;
     if ((st = dev_alloc(c, &c->slot_uid_d, (size_t)c->nslots, "slot map")) != MMOC_OK) return st;
-    const bool f32 = c->prec == MMOC_FP32_MIXED;
+    const bool f32 = c->prec != MMOC_FP64;
     const size_t elem = f32 ? sizeof(float) : sizeof(double);
     const int na = (d == 3 && f32) ? 3 : 2;  // components in the va records
     if ((uint64_t)c->nslots * na * elem >= (1ull << 32))
         return fail(c, MMOC_E_ARG, "mesh too large: field arrays must stay below 4 GiB for 32-bit slot offsets");
-    auto alloc_clear = [&](void** p, size_t bytes, const char* what) -> mmoc_status {
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess) {
-            *p = nullptr;
-            return hip_fail(c, e, what);
-        }
-        HIPCHK(c, hipMemsetAsync(*p, 0, bytes, c->stream), what);
-        return MMOC_OK;
-    };
-    for (int l = 0; l < 2; ++l) {
-        if ((st = alloc_clear(&c->va_d[l], (size_t)c->nslots * na * elem, "velocity arrays")) != MMOC_OK) return st;
-        if (d == 3 && !f32 && (st = alloc_clear(&c->vb_d[l], (size_t)c->nslots * elem, "velocity arrays")) != MMOC_OK)
-            return st;
-    }
-    if ((st = alloc_clear(&c->cs_d, (size_t)c->nslots * elem, "scalar array")) != MMOC_OK) return st;
+    if ((st = alloc_velocity_levels(c, c->lev_cap)) != MMOC_OK) return st;
+    if ((st = alloc_clear(c, &c->cs_d, (size_t)c->nslots * elem, "scalar array")) != MMOC_OK) return st;
     HIPCHK(c, hipMemcpyAsync(c->geo_d, geo.data(), sizeof(MacroGeo) * nm, hipMemcpyHostToDevice, c->stream), "upload geometry");
     HIPCHK(c, hipMemcpyAsync(c->owned_d, owned.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, c->stream), "upload particles");
     HIPCHK(c, hipMemcpyAsync(c->slot_uid_d, slot_uid.data(), sizeof(int32_t) * c->nslots, hipMemcpyHostToDevice, c->stream),
@@ -422,7 +484,7 @@ mmoc_status mmoc_dof_coords(mmoc_ctx* c, double* xyz)
     if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
     mmoc_status st = check_dev(c, xyz, sizeof(double) * c->dim * c->N, 8, "xyz_dev");
     if (st != MMOC_OK) return st;
-    HIPCHK(c, mmoc::launch_dof_coords(c->dim, c->blend, c->geo_d, c->owned_d, c->N, c->n, xyz, c->stream), "dof_coords");
+    HIPCHK(c, mmoc::launch_dof_coords(c->dim, c->blend, c->geo_d, c->owned_d, c->N, c->m, xyz, c->stream), "dof_coords");
     return MMOC_OK;
 }
 
@@ -430,15 +492,19 @@ mmoc_status mmoc_set_velocity(mmoc_ctx* c, int level, const double* u)
 {
     if (!c) return MMOC_E_ARG;
     if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
-    if (level != 0 && level != 1) return fail(c, MMOC_E_ARG, "level must be 0 or 1");
-    if (c->stationary && level == 1) return fail(c, MMOC_E_STATE, "stationary velocity: only level 0 is used");
+    if (level < 0 || level >= c->lev_cap)
+        return fail(c, MMOC_E_ARG, "level must be in [0, %d] (the velocity levels held)", c->lev_cap - 1);
+    if (c->stationary && level != 0) return fail(c, MMOC_E_STATE, "stationary velocity: only level 0 is used");
     mmoc_status st = check_dev(c, u, sizeof(double) * c->dim * c->N, 8, "u_dev");
     if (st != MMOC_OK) return st;
-    const int L = level ^ c->swap;
+    const int L = phys_level(c, level);
+    const size_t elem = c->prec == MMOC_FP64 ? sizeof(double) : sizeof(float);
+    void* va = static_cast<char*>(c->va_all) + (size_t)L * c->va_lstride * elem;
+    void* vb = c->vb_all ? static_cast<char*>(c->vb_all) + (size_t)L * c->vb_lstride * elem : nullptr;
     mmoc::ScatterDst d{};
     if (c->dim == 3 && c->prec == MMOC_FP64) {
-        d.dst[0] = d.dst[1] = c->va_d[L];
-        d.dst[2] = c->vb_d[L];
+        d.dst[0] = d.dst[1] = va;
+        d.dst[2] = vb;
         d.stride[0] = d.stride[1] = 2;
         d.stride[2] = 1;
         d.off[0] = 0;
@@ -447,12 +513,12 @@ mmoc_status mmoc_set_velocity(mmoc_ctx* c, int level, const double* u)
     } else {
         const int na = c->dim == 3 ? 3 : 2;
         for (int i = 0; i < c->dim; ++i) {
-            d.dst[i] = c->va_d[L];
+            d.dst[i] = va;
             d.stride[i] = na;
             d.off[i] = i;
         }
     }
-    HIPCHK(c, mmoc::launch_scatter(c->dim, c->slot_uid_d, c->nslots, u, c->N, d, c->prec == MMOC_FP32_MIXED, c->stream),
+    HIPCHK(c, mmoc::launch_scatter(c->dim, c->slot_uid_d, c->nslots, u, c->N, d, c->prec != MMOC_FP64, c->stream),
            "set_velocity");
     c->vel_set[level] = true;
     return MMOC_OK;
@@ -462,7 +528,8 @@ mmoc_status mmoc_set_stationary(mmoc_ctx* c, int on)
 {
     if (!c) return MMOC_E_ARG;
     c->stationary = on != 0;
-    if (c->stationary) c->vel_set[1] = false;
+    if (c->stationary)
+        for (int l = 1; l < c->lev_cap; ++l) c->vel_set[l] = 0;
     return MMOC_OK;
 }
 
@@ -472,9 +539,11 @@ mmoc_status mmoc_swap_velocity_levels(mmoc_ctx* c)
     if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
     if (c->stationary) return fail(c, MMOC_E_STATE, "stationary velocity has one level");
     if (!c->vel_set[1]) return fail(c, MMOC_E_STATE, "velocity level 1 is not set");
-    c->swap ^= 1;
-    c->vel_set[0] = true;
-    c->vel_set[1] = false;
+    // the ring turns by one: logical level l takes the data of level l + 1,
+    // and the last level (the oldest data) must be set again
+    c->rot = (c->rot + 1) % c->lev_cap;
+    for (int l = 0; l + 1 < c->lev_cap; ++l) c->vel_set[l] = c->vel_set[l + 1];
+    c->vel_set[c->lev_cap - 1] = 0;
     return MMOC_OK;
 }
 
@@ -488,7 +557,7 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
     d.dst[0] = c->cs_d;
     d.stride[0] = 1;
     d.off[0] = 0;
-    HIPCHK(c, mmoc::launch_scatter(1, c->slot_uid_d, c->nslots, cs, c->N, d, c->prec == MMOC_FP32_MIXED, c->stream),
+    HIPCHK(c, mmoc::launch_scatter(1, c->slot_uid_d, c->nslots, cs, c->N, d, c->prec != MMOC_FP64, c->stream),
            "set_scalar");
     c->scalar_set = true;
     return MMOC_OK;
@@ -499,7 +568,7 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
 // Shared by the plain and the surrogate step: launches the RK4 tracer on n
 // particles whose unique ids are order[0..n) (all particles: the lane order).
 mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* order,
-                              int64_t n, const unsigned long long* n_dev)
+                              int64_t n, const unsigned long long* n_dev, int first, int n_int)
 {
     auto fill = [&](auto& a) {
         a.geo = c->geo_d;
@@ -512,6 +581,8 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.npm = (int)c->npm;
         a.nlev = c->stationary ? 1 : 2;
         a.level_n = c->n;
+        a.ord = c->opt.order;
+        a.lat_m = c->m;
         a.substeps = substeps;
         a.max_hops = c->opt.max_hops;
         a.dt = dt;
@@ -520,24 +591,30 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.eps32_micro = c->opt.eps32_micro;
         a.X = X;
         a.stats = c->stats_d;
+        a.rk = c->rk;
+        a.lsa = c->va_lstride;
+        a.lsb = c->vb_lstride;
+        a.lev_cap = c->lev_cap;
+        a.rot = c->rot;
+        a.first = first;
+        a.n_int = n_int;
     };
-    if (c->prec == MMOC_FP32_MIXED) {
+    if (c->prec != MMOC_FP64) {
         mmoc::TraceArgs<float> a{};
         fill(a);
-        for (int l = 0; l < 2; ++l) {
-            a.va[l] = (const float*)c->va_d[l ^ c->swap];
-            a.vb[l] = (const float*)c->vb_d[l ^ c->swap];
-        }
+        a.va = (const float*)c->va_all;
+        a.vb = (const float*)c->vb_all;
         a.cs = (const float*)c->cs_d;
         a.c_hat = (float*)c_hat;
-        HIPCHK(c, mmoc::launch_trace_fp32(c->dim, c->blend, a, c->stream), "trace (fp32 mixed)");
+        if (c->prec == MMOC_FP32_MIXED)
+            HIPCHK(c, mmoc::launch_trace_fp32(c->dim, c->blend, a, c->stream), "trace (fp32 mixed)");
+        else
+            HIPCHK(c, mmoc::launch_trace_fp32_fields(c->dim, c->blend, a, c->stream), "trace (fp32 fields)");
     } else {
         mmoc::TraceArgs<double> a{};
         fill(a);
-        for (int l = 0; l < 2; ++l) {
-            a.va[l] = (const double*)c->va_d[l ^ c->swap];
-            a.vb[l] = (const double*)c->vb_d[l ^ c->swap];
-        }
+        a.va = (const double*)c->va_all;
+        a.vb = (const double*)c->vb_all;
         a.cs = (const double*)c->cs_d;
         a.c_hat = (double*)c_hat;
         HIPCHK(c, mmoc::launch_trace_fp64(c->dim, c->blend, a, c->stream), "trace (fp64)");
@@ -553,7 +630,7 @@ mmoc_status mmoc_check_step_args(mmoc_ctx* c, double dt, int substeps, void* c_h
     if (!c->scalar_set) return fail(c, MMOC_E_STATE, "scalar is not set");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(c, MMOC_E_ARG, "dt must be positive and finite");
     if (substeps < 1 || substeps > (1 << 20)) return fail(c, MMOC_E_ARG, "substeps must be in [1, 2^20]");
-    const size_t es = c->prec == MMOC_FP32_MIXED ? sizeof(float) : sizeof(double);
+    const size_t es = c->prec == MMOC_FP64 ? sizeof(double) : sizeof(float);
     mmoc_status st = check_dev(c, c_hat, es * c->N, es, "c_hat_dev");
     if (st != MMOC_OK) return st;
     if (X && (st = check_dev(c, X, sizeof(double) * c->dim * c->N, 8, "X_dev")) != MMOC_OK) return st;
@@ -568,6 +645,42 @@ mmoc_status mmoc_trace_step(mmoc_ctx* c, double dt, int substeps, void* c_hat, d
     mmoc_status st = mmoc_check_step_args(c, dt, substeps, c_hat, X);
     if (st != MMOC_OK) return st;
     return mmoc_launch_trace(c, dt, substeps, c_hat, X, nullptr, c->N);
+}
+
+mmoc_status mmoc_set_level_count(mmoc_ctx* c, int levels)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (levels < 2 || levels > 65536) return fail(c, MMOC_E_ARG, "levels must be in [2, 65536]");
+    if (levels == c->lev_cap) return MMOC_OK;
+    return alloc_velocity_levels(c, levels);
+}
+
+mmoc_status mmoc_trace_span(mmoc_ctx* c, int first, int n_int, double dt, int substeps, void* c_hat, double* X)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (n_int < 1) return fail(c, MMOC_E_ARG, "n_int must be at least 1");
+    if (c->stationary) {
+        if (first != 0) return fail(c, MMOC_E_ARG, "a stationary velocity has level 0 only");
+        if (!c->vel_set[0]) return fail(c, MMOC_E_STATE, "velocity level 0 is not set");
+    } else {
+        if (first < 0 || first + n_int >= c->lev_cap)
+            return fail(c, MMOC_E_ARG, "levels %d..%d are not all held (%d levels)", first, first + n_int, c->lev_cap);
+        for (int l = first; l <= first + n_int; ++l)
+            if (!c->vel_set[l]) return fail(c, MMOC_E_STATE, "velocity level %d is not set", l);
+    }
+    if (!c->scalar_set) return fail(c, MMOC_E_STATE, "scalar is not set");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, MMOC_E_ARG, "dt must be positive and finite");
+    if (substeps < 1 || (int64_t)substeps * n_int > (1 << 20))
+        return fail(c, MMOC_E_ARG, "substeps * n_int must be in [1, 2^20]");
+    const size_t es = c->prec == MMOC_FP64 ? sizeof(double) : sizeof(float);
+    mmoc_status st = check_dev(c, c_hat, es * c->N, es, "c_hat_dev");
+    if (st != MMOC_OK) return st;
+    if (X && (st = check_dev(c, X, sizeof(double) * c->dim * c->N, 8, "X_dev")) != MMOC_OK) return st;
+    // a stationary field: one level, the whole span is one longer trace
+    if (c->stationary) return mmoc_launch_trace(c, dt * n_int, substeps * n_int, c_hat, X, nullptr, c->N);
+    return mmoc_launch_trace(c, dt, substeps, c_hat, X, nullptr, c->N, nullptr, first, n_int);
 }
 
 mmoc_status mmoc_get_stats(mmoc_ctx* c, mmoc_stats* out)
@@ -629,11 +742,9 @@ void free_all(mmoc_ctx* c)
     (void)hipFree(c->geo_d);
     (void)hipFree(c->owned_d);
     (void)hipFree(c->slot_uid_d);
-    for (int l = 0; l < 2; ++l) {
-        (void)hipFree(c->va_d[l]);
-        (void)hipFree(c->vb_d[l]);
-        c->va_d[l] = c->vb_d[l] = nullptr;
-    }
+    (void)hipFree(c->va_all);
+    (void)hipFree(c->vb_all);
+    c->va_all = c->vb_all = nullptr;
     (void)hipFree(c->cs_d);
     (void)hipFree(c->stats_d);
     (void)hipFree(c->red_d);

@@ -60,30 +60,47 @@ enum LaneFlag : unsigned {
 
 // Arguments of the trace kernels.  Fields live in per-component arrays over
 // the block slots (slot = macro * npm + lattice index, macro-major, lattice
-// nodes of a macro in lexicographic order), one set per velocity level:
+// nodes of a macro in lexicographic order), one set per velocity level (a
+// ring of lev_cap levels, equally spaced in time; the stage times select the
+// two levels around them):
 //   3D float64: va = (u_x, u_y) pairs (16 B), vb = u_z (8 B)
 //   3D float32: va = (u_x, u_y, u_z) triples (12 B), vb unused
 //   2D        : va = (u_x, u_y) pairs, vb unused
 //   cs        : the scalar c at t_n
 // Small records keep the number of distinct cache lines per wave-level load
-// low, which is what the gather throughput depends on.  va[0]/vb[0] hold t_n
-// and va[1]/vb[1] t_{n+1} (the host swaps pointers between steps).
+// low, which is what the gather throughput depends on.
+// Butcher tableau of a general explicit Runge-Kutta method (s > 0), or the
+// classical RK4 of the specialised path (s == 0).  a is row-major
+// [kMaxStages][kMaxStages], strictly lower triangular.
+constexpr int kMaxStages = 7;
+struct RKTab {
+    int s;
+    double a[kMaxStages * kMaxStages];
+    double b[kMaxStages];
+    double c[kMaxStages];
+};
+
 template <typename T>
 struct TraceArgs {
     const MacroGeo* geo;
     const uint64_t* owned;   // [n_unique] (macro, I, J, K) per DoF, unique order
     const int32_t* order;    // [n] unique ids in lane order, or null: lane t traces DoF t
     const unsigned long long* n_dev;  // if set: lanes t >= *n_dev do nothing (device-side count)
-    const T* va[2];
-    const T* vb[2];
+    const T* va;             // velocity ring, physical slot 0 (see lev_cap / rot / lsa / lsb)
+    const T* vb;
     const T* cs;
+    int64_t lsa, lsb;        // elements per velocity level in va / vb
+    int lev_cap, rot;        // ring size and physical slot of logical level 0
+    int first, n_int;        // trace from logical level first + n_int back to first
     int64_t n;               // particles traced by this launch (lanes)
     int64_t xstride;         // n_unique: stride of X and extent of c_hat
     int nm;                  // macros
     int npm;                 // lattice nodes per macro
     int nlev;                // 1 (stationary) or 2
     int level_n;             // micro edges per macro edge, 2^level
-    int substeps;
+    int ord;                 // element order: 2 (P2) or 1 (P1)
+    int lat_m;               // DoF lattice resolution, order * level_n
+    int substeps;            // RK sub-steps per interval (dt = interval length)
     int max_hops;
     double dt;
     double eps_in;
@@ -92,19 +109,23 @@ struct TraceArgs {
     T* c_hat;                // [n_unique] or null
     double* X;               // [dim][n_unique] or null
     unsigned long long* stats;
+    RKTab rk;                // float64-arithmetic kernels only
 };
 
 // Launchers (kernels in mmoc_kernels.hip).  Each validates nothing: the host
 // side checks every argument before calling them.
 hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s);
 hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
+// float32 records, float64 arithmetic (MMOC_FP32_FIELDS)
+hipError_t launch_trace_fp32_fields(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
 // chat = c_h^n(X) for every particle, X given ([dim][n]); the walk starts in
 // the particle's own macro (uses geo, owned, cs, n, nm, npm, level_n,
 // max_hops, eps_in, eps32_*, c_hat, X (read), stats)
 hipError_t launch_scalar_eval_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s);
 hipError_t launch_scalar_eval_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
+hipError_t launch_scalar_eval_fp32_fields(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
 hipError_t launch_dof_coords(int dim, int blend, const MacroGeo* geo, const uint64_t* owned,
-                             int64_t n, int level_n, double* out, hipStream_t s);
+                             int64_t n, int lat_m, double* out, hipStream_t s);
 // Copy of a unique-layout field into block slots: component i of DoF
 // slot_uid[slot] goes to dst[i][slot * stride[i] + off[i]] (i < ncomp).
 struct ScatterDst {
@@ -124,10 +145,15 @@ struct MassRef {
 int64_t mass_inner_blocks(int dim, int nm, int n);
 // out[0] = (a - a_sub)^T M (b - b_sub) over the whole refined mesh (a null:
 // ones; a_sub, b_sub null: zero); partial holds mass_inner_blocks doubles
-hipError_t launch_mass_inner(int dim, const MacroGeo* geo, const int32_t* slot_uid, int64_t npm, int nm, int n,
-                             const MassRef& R, const double* a, const double* a_sub, const double* b,
+hipError_t launch_mass_inner(int dim, int ord, const MacroGeo* geo, const int32_t* slot_uid, int64_t npm, int nm,
+                             int n, const MassRef& R, const double* a, const double* a_sub, const double* b,
                              const double* b_sub, double* partial, double* out, hipStream_t s);
 // out[0] = min c, out[1] = max c (NaNs skipped); partial holds 2 nblocks doubles
 hipError_t launch_range(const double* c, int64_t n, double* partial, int64_t nblocks, double* out, hipStream_t s);
+// out[0] = largest nodal speed of one velocity level in block slots (va
+// records of `stride` components, the last component in vb when vb is set);
+// partial holds nblocks doubles
+hipError_t launch_speed_max(const void* va, const void* vb, int fp32, int dim, int stride, int64_t nslots,
+                            double* partial, int64_t nblocks, double* out, hipStream_t s);
 
 }  // namespace mmoc

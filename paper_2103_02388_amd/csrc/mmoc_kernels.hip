@@ -14,14 +14,14 @@ constexpr int kBlock = 256;
 template <int DIM, int BLEND>
 __global__ __launch_bounds__(kBlock) void dof_coords_kernel(const MacroGeo* __restrict__ geo,
                                                             const uint64_t* __restrict__ owned, int64_t n,
-                                                            int level_n, double* __restrict__ out)
+                                                            int lat_m, double* __restrict__ out)
 {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= n) return;
     const uint64_t e = owned[t];
     const int M = (int)(e >> 36);
     const int I = (int)((e >> 24) & 0xfffu), J = (int)((e >> 12) & 0xfffu), K = (int)(e & 0xfffu);
-    const double invm = 1.0 / (double)(2 * level_n);
+    const double invm = 1.0 / (double)lat_m;
     double s[3];
     if constexpr (DIM == 2) {
         s[0] = (double)(I - J) * invm;
@@ -42,9 +42,12 @@ __global__ __launch_bounds__(kBlock) void dof_coords_kernel(const MacroGeo* __re
     }
     double f = 1.0;
     if constexpr (BLEND) {
-        const double nx = G.pn[0] * p[0] + G.pn[1] * p[1] + G.pn[2] * p[2];
-        const double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-        f = nx / (G.pc * r);
+        double nx = G.pn[0] * p[0] + G.pn[1] * p[1], r2 = p[0] * p[0] + p[1] * p[1];
+        if constexpr (DIM == 3) {
+            nx += G.pn[2] * p[2];
+            r2 += p[2] * p[2];
+        }
+        f = nx / (G.pc * sqrt(r2));
     }
 #pragma unroll
     for (int i = 0; i < DIM; ++i) out[(int64_t)i * n + t] = BLEND ? p[i] * f : p[i];
@@ -67,13 +70,14 @@ inline unsigned grid_plain(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 }  // namespace
 
 hipError_t launch_dof_coords(int dim, int blend, const MacroGeo* geo, const uint64_t* owned, int64_t n,
-                             int level_n, double* out, hipStream_t s)
+                             int lat_m, double* out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const dim3 grid(grid_plain(n)), block(kBlock);
-    if (dim == 2) dof_coords_kernel<2, 0><<<grid, block, 0, s>>>(geo, owned, n, level_n, out);
-    else if (!blend) dof_coords_kernel<3, 0><<<grid, block, 0, s>>>(geo, owned, n, level_n, out);
-    else dof_coords_kernel<3, 1><<<grid, block, 0, s>>>(geo, owned, n, level_n, out);
+    if (dim == 2 && !blend) dof_coords_kernel<2, 0><<<grid, block, 0, s>>>(geo, owned, n, lat_m, out);
+    else if (dim == 2) dof_coords_kernel<2, 1><<<grid, block, 0, s>>>(geo, owned, n, lat_m, out);
+    else if (!blend) dof_coords_kernel<3, 0><<<grid, block, 0, s>>>(geo, owned, n, lat_m, out);
+    else dof_coords_kernel<3, 1><<<grid, block, 0, s>>>(geo, owned, n, lat_m, out);
     return hipGetLastError();
 }
 

@@ -10,11 +10,11 @@
 
 namespace {
 
-// P2 mass matrix of a unit-volume simplex from the moments of the
-// barycentric coordinates: int_T lambda^alpha = |T| d! alpha! / (d + |alpha|)!.
-// The basis is phi_a = lambda_a (2 lambda_a - 1) at the vertices and
-// phi_ab = 4 lambda_a lambda_b at the edge midpoints.
-mmoc::MassRef p2_mass_unit(int d)
+// Mass matrix of a unit-volume simplex from the moments of the barycentric
+// coordinates: int_T lambda^alpha = |T| d! alpha! / (d + |alpha|)!.  The P2
+// basis is phi_a = lambda_a (2 lambda_a - 1) at the vertices and phi_ab =
+// 4 lambda_a lambda_b at the edge midpoints; the P1 basis is phi_a = lambda_a.
+mmoc::MassRef mass_unit(int d, int ord)
 {
     using Mono = std::vector<int>;  // exponent of each barycentric coordinate
     using Poly = std::map<Mono, double>;
@@ -25,11 +25,15 @@ mmoc::MassRef p2_mass_unit(int d)
         Mono sq(nv, 0), li(nv, 0);
         sq[a] = 2;
         li[a] = 1;
-        p[sq] = 2.0;
-        p[li] = -1.0;
+        if (ord == 2) {
+            p[sq] = 2.0;
+            p[li] = -1.0;
+        } else {
+            p[li] = 1.0;
+        }
         basis.push_back(p);
     }
-    for (int a = 0; a < nv; ++a)
+    for (int a = 0; a < nv && ord == 2; ++a)
         for (int b = a + 1; b < nv; ++b) {
             Poly p;
             Mono e(nv, 0);
@@ -107,11 +111,14 @@ mmoc_status mmoc_mass_inner(mmoc_ctx* c, const double* a, const double* a_sub, c
     const int64_t nb = mmoc::mass_inner_blocks(c->dim, c->nm, c->n);
     mmoc_status st = ensure_reduction(c, std::max<int64_t>(nb, 2 * kRangeBlocks) + 2);
     if (st != MMOC_OK) return st;
-    static const mmoc::MassRef R2 = p2_mass_unit(2), R3 = p2_mass_unit(3);
+    static const mmoc::MassRef R2 = mass_unit(2, 2), R3 = mass_unit(3, 2), Q2 = mass_unit(2, 1),
+                               Q3 = mass_unit(3, 1);
+    const int ord = c->opt.order;
+    const mmoc::MassRef& R = ord == 2 ? (c->dim == 3 ? R3 : R2) : (c->dim == 3 ? Q3 : Q2);
     double* res = c->red_d + c->red_cap - 2;
     HIPCHK(c,
-           mmoc::launch_mass_inner(c->dim, c->geo_d, c->slot_uid_d, c->npm, c->nm, c->n, c->dim == 3 ? R3 : R2, a,
-                                   a_sub, b, b_sub, c->red_d, res, c->stream),
+           mmoc::launch_mass_inner(c->dim, ord, c->geo_d, c->slot_uid_d, c->npm, c->nm, c->n, R, a, a_sub, b, b_sub,
+                                   c->red_d, res, c->stream),
            "mass inner product");
     HIPCHK(c, hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, c->stream), "mass inner product");
     HIPCHK(c, hipStreamSynchronize(c->stream), "mass inner product");
@@ -175,6 +182,68 @@ mmoc_status mmoc_lookback_run(mmoc_ctx* c, double tau, int substeps, int64_t n_s
                hipMemcpyAsync(c_out, ring + (size_t)(n_steps % ring_len) * c->N, fb, hipMemcpyDeviceToDevice,
                               c->stream),
                "look-back result");
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_set_rk_tableau(mmoc_ctx* c, int stages, const double* a, const double* b, const double* cn)
+{
+    if (!c) return MMOC_E_ARG;
+    if (stages == 0) {
+        c->rk = mmoc::RKTab{};
+        return MMOC_OK;
+    }
+    if (c->prec == MMOC_FP32_MIXED)
+        return fail(c, MMOC_E_UNSUPPORTED, "general RK tableaux run on the float64-arithmetic tracers only");
+    if (stages < 1 || stages > mmoc::kMaxStages)
+        return fail(c, MMOC_E_ARG, "stages must be in [1, %d] (0 restores RK4)", mmoc::kMaxStages);
+    if (!a || !b || !cn) return fail(c, MMOC_E_ARG, "a, b and c must be host arrays");
+    mmoc::RKTab t{};
+    t.s = stages;
+    for (int i = 0; i < stages; ++i) {
+        if (!std::isfinite(b[i]) || !std::isfinite(cn[i])) return fail(c, MMOC_E_ARG, "non-finite tableau entry");
+        t.b[i] = b[i];
+        t.c[i] = cn[i];
+        for (int l = 0; l < i; ++l) {
+            const double v = a[i * stages + l];
+            if (!std::isfinite(v)) return fail(c, MMOC_E_ARG, "non-finite tableau entry");
+            t.a[i * mmoc::kMaxStages + l] = v;
+        }
+        for (int l = i; l < stages; ++l)
+            if (a[i * stages + l] != 0.0)
+                return fail(c, MMOC_E_ARG, "a must be strictly lower triangular (explicit method)");
+    }
+    if (cn[0] != 0.0) return fail(c, MMOC_E_ARG, "c[0] must be 0 (explicit method)");
+    c->rk = t;
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_cfl_time_step(mmoc_ctx* c, double cfl, int level, double* tau, double* umax, double* hmin)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (level < 0 || level >= c->lev_cap) return fail(c, MMOC_E_ARG, "level %d is not held", level);
+    if (!c->vel_set[level]) return fail(c, MMOC_E_STATE, "velocity level %d is not set", level);
+    if (!(cfl > 0) || !std::isfinite(cfl)) return fail(c, MMOC_E_ARG, "cfl must be positive and finite");
+    const int64_t nb = mmoc::mass_inner_blocks(c->dim, c->nm, c->n);
+    mmoc_status st = ensure_reduction(c, std::max<int64_t>(nb, 2 * kRangeBlocks) + 2);
+    if (st != MMOC_OK) return st;
+    const int L = phys_level(c, level);
+    const bool split = c->dim == 3 && c->prec == MMOC_FP64;  // (x, y) pairs + z
+    const int stride = split ? 2 : (c->dim == 3 ? 3 : 2);
+    const size_t elem = c->prec == MMOC_FP64 ? sizeof(double) : sizeof(float);
+    const void* va = static_cast<const char*>(c->va_all) + (size_t)L * c->va_lstride * elem;
+    const void* vb = split ? static_cast<const char*>(c->vb_all) + (size_t)L * c->vb_lstride * elem : nullptr;
+    double* res = c->red_d + c->red_cap - 2;
+    HIPCHK(c,
+           mmoc::launch_speed_max(va, vb, c->prec != MMOC_FP64, c->dim, stride, c->nslots, c->red_d, kRangeBlocks,
+                                  res, c->stream),
+           "largest speed");
+    double u = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&u, res, sizeof u, hipMemcpyDeviceToHost, c->stream), "largest speed");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "largest speed");
+    if (umax) *umax = u;
+    if (hmin) *hmin = c->hmin;
+    if (tau) *tau = u > 0.0 ? cfl * c->hmin / u : INFINITY;
     return MMOC_OK;
 }
 

@@ -1,7 +1,7 @@
 // mmoc_metrics.hip -- the accuracy measures of the paper's benchmarks
 // (Sec. 3.1) on the GPU: the discrete H0 inner product a^T M b with the P2
-// mass matrix M of the refined mesh, and the range (min, max) of a nodal
-// field.  Both reduce in two passes with a fixed summation order, so a result
+// (or P1) mass matrix M of the refined mesh, and the range (min, max) of a
+// nodal field.  Both reduce in two passes with a fixed summation order, so a result
 // does not depend on the schedule.
 //
 // The mass matrix is assembled on the fly, one micro simplex at a time: a
@@ -69,7 +69,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
     return s;
 }
 
-template <int DIM>
+template <int DIM, int ORD>
 __global__ __launch_bounds__(kMB) void mass_inner_kernel(const MacroGeo* __restrict__ geo,
                                                          const int32_t* __restrict__ slot_uid, int64_t npm, int n,
                                                          int64_t cubes_per_macro, int64_t total, MassRef R,
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kMB) void mass_inner_kernel(const MacroGeo* __restr
                                                          double* __restrict__ partial)
 {
     constexpr int NV = DIM + 1;
-    constexpr int NN = (DIM + 1) * (DIM + 2) / 2;
+    constexpr int NN = ORD == 2 ? (DIM + 1) * (DIM + 2) / 2 : DIM + 1;
     __shared__ double sh[kMB / 64];
     const int64_t t = (int64_t)blockIdx.x * kMB + threadIdx.x;
     double acc = 0.0;
@@ -116,8 +116,11 @@ __global__ __launch_bounds__(kMB) void mass_inner_kernel(const MacroGeo* __restr
             if (!ok) continue;
             double av[NN], bv[NN];
             int c = 0;
+            // P2 nodes V_a + V_b on the 2n-lattice; P1 nodes V_a on the n-lattice
             auto load = [&](int A, int Bn) {
-                const int I = V[A][0] + V[Bn][0], J = V[A][1] + V[Bn][1], K = V[A][2] + V[Bn][2];
+                const int I = ORD == 2 ? V[A][0] + V[Bn][0] : V[A][0];
+                const int J = ORD == 2 ? V[A][1] + V[Bn][1] : V[A][1];
+                const int K = ORD == 2 ? V[A][2] + V[Bn][2] : V[A][2];
                 const int64_t idx = DIM == 3 ? tet64(I) + tri64(J) + K : tri64(I) + J;
                 const int64_t u = slot_uid[base + idx];
                 av[c] = nodal(a, a_sub, u);
@@ -125,8 +128,9 @@ __global__ __launch_bounds__(kMB) void mass_inner_kernel(const MacroGeo* __restr
                 ++c;
             };
             for (int s = 0; s < NV; ++s) load(s, s);
-            for (int s = 0; s < NV; ++s)
-                for (int r = s + 1; r < NV; ++r) load(s, r);
+            if constexpr (ORD == 2)
+                for (int s = 0; s < NV; ++s)
+                    for (int r = s + 1; r < NV; ++r) load(s, r);
             double quad = 0.0;
             for (int i = 0; i < NN; ++i) {
                 double row = 0.0;
@@ -203,7 +207,63 @@ __global__ __launch_bounds__(64) void range_final_kernel(const double* __restric
     }
 }
 
+// per-block largest nodal speed |u| of one velocity level stored in block
+// slots: (x, y) pairs in va (stride 2) with z in vb, or (x, y, z) triples
+// in va (stride 3) with vb null
+template <typename T>
+__global__ __launch_bounds__(kMB) void speed_max_kernel(const T* __restrict__ va, const T* __restrict__ vb, int dim,
+                                                        int stride, int64_t nslots, double* __restrict__ pmax)
+{
+    __shared__ double sh[kMB / 64];
+    double hi = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * kMB + threadIdx.x; q < nslots; q += (int64_t)gridDim.x * kMB) {
+        double s2 = 0.0;
+        for (int i = 0; i < (vb ? 2 : dim); ++i) {
+            const double v = (double)va[q * stride + i];
+            s2 += v * v;
+        }
+        if (vb) {
+            const double v = (double)vb[q];
+            s2 += v * v;
+        }
+        hi = fmax(hi, s2);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) hi = fmax(hi, __shfl_down(hi, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = hi;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kMB / 64; ++i) hi = fmax(hi, sh[i]);
+        pmax[blockIdx.x] = hi;
+    }
+}
+
+__global__ __launch_bounds__(64) void max_final_kernel(const double* __restrict__ p, int64_t count,
+                                                       double* __restrict__ out)
+{
+    double hi = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 64) hi = fmax(hi, p[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) hi = fmax(hi, __shfl_down(hi, off, 64));
+    if (threadIdx.x == 0) out[0] = sqrt(hi);
+}
+
 }  // namespace
+
+hipError_t launch_speed_max(const void* va, const void* vb, int fp32, int dim, int stride, int64_t nslots,
+                            double* partial, int64_t nblocks, double* out, hipStream_t s)
+{
+    if (fp32)
+        speed_max_kernel<float><<<(unsigned)nblocks, kMB, 0, s>>>((const float*)va, (const float*)vb, dim, stride,
+                                                                  nslots, partial);
+    else
+        speed_max_kernel<double><<<(unsigned)nblocks, kMB, 0, s>>>((const double*)va, (const double*)vb, dim, stride,
+                                                                   nslots, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    max_final_kernel<<<1, 64, 0, s>>>(partial, nblocks, out);
+    return hipGetLastError();
+}
 
 int64_t mass_inner_blocks(int dim, int nm, int n)
 {
@@ -211,19 +271,25 @@ int64_t mass_inner_blocks(int dim, int nm, int n)
     return ((int64_t)nm * cubes + kMB - 1) / kMB;
 }
 
-hipError_t launch_mass_inner(int dim, const MacroGeo* geo, const int32_t* slot_uid, int64_t npm, int nm, int n,
-                             const MassRef& R, const double* a, const double* a_sub, const double* b,
+hipError_t launch_mass_inner(int dim, int ord, const MacroGeo* geo, const int32_t* slot_uid, int64_t npm, int nm,
+                             int n, const MassRef& R, const double* a, const double* a_sub, const double* b,
                              const double* b_sub, double* partial, double* out, hipStream_t s)
 {
     const int64_t cubes = dim == 3 ? (int64_t)n * (n + 1) * (n + 2) / 6 : (int64_t)n * (n + 1) / 2;
     const int64_t total = (int64_t)nm * cubes;
     const int64_t nb = mass_inner_blocks(dim, nm, n);
-    if (dim == 3)
-        mass_inner_kernel<3><<<(unsigned)nb, kMB, 0, s>>>(geo, slot_uid, npm, n, cubes, total, R, a, a_sub, b, b_sub,
-                                                          partial);
+    if (dim == 3 && ord == 2)
+        mass_inner_kernel<3, 2><<<(unsigned)nb, kMB, 0, s>>>(geo, slot_uid, npm, n, cubes, total, R, a, a_sub, b,
+                                                             b_sub, partial);
+    else if (dim == 3)
+        mass_inner_kernel<3, 1><<<(unsigned)nb, kMB, 0, s>>>(geo, slot_uid, npm, n, cubes, total, R, a, a_sub, b,
+                                                             b_sub, partial);
+    else if (ord == 2)
+        mass_inner_kernel<2, 2><<<(unsigned)nb, kMB, 0, s>>>(geo, slot_uid, npm, n, cubes, total, R, a, a_sub, b,
+                                                             b_sub, partial);
     else
-        mass_inner_kernel<2><<<(unsigned)nb, kMB, 0, s>>>(geo, slot_uid, npm, n, cubes, total, R, a, a_sub, b, b_sub,
-                                                          partial);
+        mass_inner_kernel<2, 1><<<(unsigned)nb, kMB, 0, s>>>(geo, slot_uid, npm, n, cubes, total, R, a, a_sub, b,
+                                                             b_sub, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     sum_partials_kernel<<<1, kMB, 0, s>>>(partial, nb, out);

@@ -55,7 +55,7 @@ MlpArgs args_of(mmoc_ctx* c)
     a.geo = c->geo_d;
     a.owned = c->owned_d;
     a.n = c->N;
-    a.level_n = c->n;
+    a.lat_m = c->m;
     for (int i = 0; i < 4; ++i) {
         a.lo[i] = S->lo[i];
         a.hi[i] = S->hi[i];
@@ -391,6 +391,8 @@ mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* c, double t_np1, double dt, int 
         a.nm = c->nm;
         a.npm = (int)c->npm;
         a.level_n = c->n;
+        a.ord = c->opt.order;
+        a.lat_m = c->m;
         a.max_hops = c->opt.max_hops;
         a.eps_in = c->opt.eps_in;
         a.eps32_macro = c->opt.eps32_macro;
@@ -398,12 +400,15 @@ mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* c, double t_np1, double dt, int 
         a.X = X;
         a.stats = c->stats_d;
     };
-    if (c->prec == MMOC_FP32_MIXED) {
+    if (c->prec != MMOC_FP64) {
         mmoc::TraceArgs<float> a{};
         fill(a);
         a.cs = (const float*)c->cs_d;
         a.c_hat = (float*)c_hat;
-        HIPCHK(c, mmoc::launch_scalar_eval_fp32(c->dim, c->blend, a, c->stream), "scalar evaluation");
+        if (c->prec == MMOC_FP32_MIXED)
+            HIPCHK(c, mmoc::launch_scalar_eval_fp32(c->dim, c->blend, a, c->stream), "scalar evaluation");
+        else
+            HIPCHK(c, mmoc::launch_scalar_eval_fp32_fields(c->dim, c->blend, a, c->stream), "scalar evaluation");
     } else {
         mmoc::TraceArgs<double> a{};
         fill(a);

@@ -158,11 +158,11 @@ __device__ __forceinline__ void scale_inputs(const MlpArgs& A, const double* x, 
 }
 
 // position of DoF e: x = v0 + B s (blended shells are not supported here)
-__device__ __forceinline__ void dof_pos(const MacroGeo* __restrict__ geo, uint64_t e, int level_n, double* x)
+__device__ __forceinline__ void dof_pos(const MacroGeo* __restrict__ geo, uint64_t e, int lat_m, double* x)
 {
     const int M = (int)(e >> 36);
     const int I = (int)((e >> 24) & 0xfffu), J = (int)((e >> 12) & 0xfffu), K = (int)(e & 0xfffu);
-    const double invm = 1.0 / (double)(2 * level_n);
+    const double invm = 1.0 / (double)lat_m;
     const double s[3] = {(double)(I - J) * invm, (double)(J - K) * invm, (double)K * invm};
     const MacroGeo& G = geo[M];
     for (int i = 0; i < 3; ++i) {
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(128) void infer_kernel(const MlpArgs A, double t_np
     double x[3] = {0.0, 0.0, 0.0};
     float in[4] = {0.f, 0.f, 0.f, 0.f};
     if (active) {
-        dof_pos(A.geo, A.owned[pid], A.level_n, x);
+        dof_pos(A.geo, A.owned[pid], A.lat_m, x);
         scale_inputs(A, x, t_np1, in);
     }
     float y[3];
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void record_kernel(const MlpArgs A, double t_n
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= A.n) return;
     double x[3];
-    dof_pos(A.geo, A.owned[i], A.level_n, x);
+    dof_pos(A.geo, A.owned[i], A.lat_m, x);
     float in[4];
     scale_inputs(A, x, t_np1, in);
     for (int k = 0; k < 4; ++k) in4[i * 4 + k] = in[k];

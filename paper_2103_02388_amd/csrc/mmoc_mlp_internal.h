@@ -21,7 +21,7 @@ struct MlpArgs {
     const MacroGeo* geo;
     const uint64_t* owned;
     int64_t n;            // particles (inference, record)
-    int level_n;
+    int lat_m;  // DoF lattice resolution
     double lo[4], hi[4];  // input box, mapped to [-1, 1]
     const float* p32;     // master parameters
     const __bf16* w2;     // bf16 W2 [out][in]

@@ -35,19 +35,30 @@
 
 #include <math.h>
 
+// 128-thread blocks and runs of 16 blocks per XCD: measured best across the
+// three precisions at 2.7e5 and 1.7e7 particles (the plain contiguous eighth
+// per XCD starves XCDs of the float32-mixed path's tie-band work)
 #ifndef MMOC_TRACE_BLOCK
-#define MMOC_TRACE_BLOCK 256
+#define MMOC_TRACE_BLOCK 128
 #endif
-// occupancy targets: the float64 kernel keeps its gather in flight without
-// spilling at 3 waves per SIMD, the float32 kernel fits 4
+// occupancy floors: the float64 kernels need at least 3 waves per SIMD
+// without spilling (the RK4 kernel fits 4 at 128 VGPRs), the float32-mixed
+// kernel 4
 #ifndef MMOC_WPE_FP64
 #define MMOC_WPE_FP64 3
 #endif
 #ifndef MMOC_WPE_FP32
 #define MMOC_WPE_FP32 4
 #endif
-#ifndef MMOC_XCD_REMAP
-#define MMOC_XCD_REMAP 1
+// Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// The trace kernels remap them so that each XCD receives runs of
+// MMOC_XCD_CHUNK consecutive logical blocks (neighbouring particles, hence
+// neighbouring field data in that XCD's L2), while consecutive runs go to
+// different XCDs (so that regions with more work -- walks, tie-band
+// re-locations -- are spread over all of them).  0: one contiguous eighth of
+// the range per XCD; 1: no remapping.
+#ifndef MMOC_XCD_CHUNK
+#define MMOC_XCD_CHUNK 16
 #endif
 
 namespace mmoc {
@@ -57,16 +68,24 @@ constexpr int kTB = MMOC_TRACE_BLOCK;
 
 __device__ __forceinline__ int64_t logical_block()
 {
-#if MMOC_XCD_REMAP
-    // block b runs on XCD b % 8; give each XCD one contiguous range
-    const unsigned per = gridDim.x >> 3;
-    return (int64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    const unsigned b = blockIdx.x, x = b & 7u, j = b >> 3;
+#if MMOC_XCD_CHUNK == 0
+    return (int64_t)x * (gridDim.x >> 3) + j;
 #else
-    return blockIdx.x;
+    constexpr unsigned c = MMOC_XCD_CHUNK;
+    return ((int64_t)(j / c) * 8 + x) * c + (j % c);
 #endif
 }
 
 // ------------------------------------------------------------------ geometry
+
+// a.b over the first DIM components
+template <int DIM>
+__device__ __forceinline__ double dotd(const double* a, const double* b)
+{
+    if constexpr (DIM == 2) return a[0] * b[0] + a[1] * b[1];
+    else return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
 
 template <int DIM, int BLEND>
 struct Geo64 {
@@ -85,9 +104,8 @@ struct Geo64 {
 #pragma unroll
             for (int c = 0; c < DIM; ++c) bi[r][c] = g[M].binv[r * 3 + c];
         if constexpr (BLEND) {
-            pn[0] = g[M].pn[0];
-            pn[1] = g[M].pn[1];
-            pn[2] = g[M].pn[2];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) pn[i] = g[M].pn[i];
             pc = g[M].pc;
         }
     }
@@ -97,8 +115,8 @@ struct Geo64 {
     {
         if constexpr (BLEND) {
             // Phi^-1(z) = z c |z| / (n.z)
-            const double nz = pn[0] * y[0] + pn[1] * y[1] + pn[2] * y[2];
-            const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+            const double nz = dotd<DIM>(pn, y);
+            const double r = sqrt(dotd<DIM>(y, y));
             const double f = pc * r / nz;
 #pragma unroll
             for (int i = 0; i < DIM; ++i) p[i] = fma(y[i], f, -v0[i]);
@@ -219,12 +237,14 @@ __device__ __noinline__ __attribute__((pure)) unsigned walk64(const MacroGeo* __
     return (unsigned)best | (flags << 27);
 }
 
-// ------------------------------------------------------ micro element + P2
+// ------------------------------------------------- micro element + P2 / P1
 
-template <int DIM, typename R>
+// ORD 2: P2 nodes, the vertices 0..DIM then the edges (a<b); ORD 1: P1, the
+// vertices only (Sec. 3.1: P1 and P2 Lagrange elements)
+template <int DIM, typename R, int ORD = 2>
 struct Stencil {
-    static constexpr int NN = (DIM + 1) * (DIM + 2) / 2;
-    int idx[NN];  // lattice index of the P2 nodes: vertices 0..DIM, then edges (a<b)
+    static constexpr int NN = ORD == 2 ? (DIM + 1) * (DIM + 2) / 2 : DIM + 1;
+    int idx[NN];  // lattice index of the nodes
     R phi[NN];    // shape function values
 };
 
@@ -239,8 +259,8 @@ __device__ __forceinline__ int tet_n(int x) { return (x * (x + 1) * (x + 2)) / 6
 // distance of the selection coordinates W = n w from a tie (an integer, or
 // another coordinate), which the mixed-precision path compares with its
 // micro band (1 without GAP).
-template <int DIM, typename R, bool GAP = false>
-__device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM, R>& st)
+template <int DIM, typename R, bool GAP = false, int ORD = 2>
+__device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM, R, ORD>& st)
 {
     R ssel[DIM];
     if (lmin >= R(0)) {
@@ -300,8 +320,25 @@ __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM,
     for (int a = 1; a < DIM; ++a) mu[a] = g[a - 1] - g[a];
     mu[DIM] = g[DIM - 1];
     // micro vertex a = k + sum of the first a axes in rank order, i.e.
-    // V_a[i] = k_i + [r_i < a]; node (a,b) sits at V_a + V_b in the P2
-    // lattice, 2k + delta with delta_i = [r_i < a] + [r_i < b] in {0,1,2}
+    // V_a[i] = k_i + [r_i < a]
+    if constexpr (ORD == 1) {
+        // P1: the nodes are the vertices, on the lattice of resolution n
+        const int I0 = k[0], J0 = k[1], K0 = k[2];
+        const int TI0 = DIM == 3 ? tet_n(I0) : tri_n(I0);
+        const int TI1 = TI0 + (DIM == 3 ? tri_n(I0 + 1) : I0 + 1);
+        const int TJ0 = DIM == 3 ? tri_n(J0) : J0;
+        const int TJ1 = TJ0 + (DIM == 3 ? J0 + 1 : 1);
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a) {
+            int id = ((r[0] < a) ? TI1 : TI0) + ((r[1] < a) ? TJ1 : TJ0);
+            if constexpr (DIM == 3) id += K0 + (r[2] < a);
+            st.idx[a] = id;
+            st.phi[a] = mu[a];
+        }
+        return gap;
+    }
+    // P2: node (a,b) sits at V_a + V_b in the lattice of resolution 2n,
+    // 2k + delta with delta_i = [r_i < a] + [r_i < b] in {0,1,2}
     const int I0 = 2 * k[0], J0 = 2 * k[1], K0 = 2 * k[2];
     int TI[3], TJ[3];
     if constexpr (DIM == 3) {
@@ -351,12 +388,12 @@ __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM,
 // Particle creation (step (i)): physical position of lattice node (I, J, K)
 // of macro M, x = Phi(v0 + B s), s = (I - J, J - K, K) / m.
 template <int DIM, int BLEND>
-__device__ __forceinline__ void dof_position(const MacroGeo* __restrict__ geo, uint64_t e, int level_n, int& M,
+__device__ __forceinline__ void dof_position(const MacroGeo* __restrict__ geo, uint64_t e, int lat_m, int& M,
                                              double* x)
 {
     M = (int)(e >> 36);
     const int I = (int)((e >> 24) & 0xfffu), J = (int)((e >> 12) & 0xfffu), K = (int)(e & 0xfffu);
-    const double invm = 1.0 / (double)(2 * level_n);  // exact: m is a power of two
+    const double invm = 1.0 / (double)lat_m;  // exact: m is a power of two
     double s[3];
     if constexpr (DIM == 2) {
         s[0] = (double)(I - J) * invm;
@@ -376,8 +413,8 @@ __device__ __forceinline__ void dof_position(const MacroGeo* __restrict__ geo, u
         p[i] = acc;
     }
     if constexpr (BLEND) {
-        const double nx = G.pn[0] * p[0] + G.pn[1] * p[1] + G.pn[2] * p[2];
-        const double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        const double nx = dotd<DIM>(G.pn, p);
+        const double r = sqrt(dotd<DIM>(p, p));
         const double f = nx / (G.pc * r);
 #pragma unroll
         for (int i = 0; i < DIM; ++i) x[i] = p[i] * f;
@@ -401,22 +438,57 @@ struct alignas(4) F3 {
     float x, y, z;
 };
 
-// velocity vector of one level at slot q
+// The two velocity levels around a stage time and the weight of the later
+// one.  pos counts intervals back from the trace's start, the later end of
+// interval iv = min(floor(pos), n_int - 1) is logical level first + n_int -
+// iv.  A stationary run has one level.  Uniform across the wave.
+template <typename T>
+struct Levels {
+    const T* ea;  // earlier level: va / vb records
+    const T* eb;
+    const T* la;  // later level
+    const T* lb;
+};
+
+template <int NLEV, typename T, typename R>
+__device__ __forceinline__ Levels<T> levels_at(const TraceArgs<T>& A, double pos, R& theta)
+{
+    Levels<T> L;
+    if constexpr (NLEV == 1) {
+        const int p = (A.rot + A.first) % A.lev_cap;
+        L.ea = L.la = A.va + (int64_t)p * A.lsa;
+        L.eb = L.lb = A.vb + (int64_t)p * A.lsb;
+        theta = R(1);
+    } else {
+        int iv = (int)pos;
+        iv = iv < A.n_int - 1 ? iv : A.n_int - 1;
+        theta = (R)(1.0 - (pos - (double)iv));
+        const int late = (A.rot + A.first + A.n_int - iv) % A.lev_cap;
+        const int early = (late + A.lev_cap - 1) % A.lev_cap;
+        L.la = A.va + (int64_t)late * A.lsa;
+        L.lb = A.vb + (int64_t)late * A.lsb;
+        L.ea = A.va + (int64_t)early * A.lsa;
+        L.eb = A.vb + (int64_t)early * A.lsb;
+    }
+    return L;
+}
+
+// velocity vector of one level (records va, vb) at slot q
 template <int DIM, typename T>
-__device__ __forceinline__ void load_vec(const TraceArgs<T>& A, int L, uint32_t q, T* u)
+__device__ __forceinline__ void load_vec(const T* va, const T* vb, uint32_t q, T* u)
 {
     if constexpr (sizeof(T) == 8) {
-        const double2 xy = ldv<double2>(A.va[L], q * 16u);
+        const double2 xy = ldv<double2>(va, q * 16u);
         u[0] = xy.x;
         u[1] = xy.y;
-        if constexpr (DIM == 3) u[2] = ldv<double>(A.vb[L], q * 8u);
+        if constexpr (DIM == 3) u[2] = ldv<double>(vb, q * 8u);
     } else if constexpr (DIM == 3) {
-        const F3 v = ldv<F3>(A.va[L], q * 12u);
+        const F3 v = ldv<F3>(va, q * 12u);
         u[0] = v.x;
         u[1] = v.y;
         u[2] = v.z;
     } else {
-        const float2 xy = ldv<float2>(A.va[L], q * 8u);
+        const float2 xy = ldv<float2>(va, q * 8u);
         u[0] = xy.x;
         u[1] = xy.y;
     }
@@ -424,11 +496,11 @@ __device__ __forceinline__ void load_vec(const TraceArgs<T>& A, int L, uint32_t 
 
 // Velocity at a stage point: P2 sums of both levels weighted (1 - theta,
 // theta), or the single level of a stationary run.
-template <int DIM, int NLEV, typename T, typename R>
-__device__ __forceinline__ void gather_vel(const TraceArgs<T>& A, uint32_t mbase, const Stencil<DIM, R>& st, R theta,
-                                           R* k)
+template <int DIM, int NLEV, typename T, typename R, int ORD>
+__device__ __forceinline__ void gather_vel(const Levels<T>& Lv, uint32_t mbase, const Stencil<DIM, R, ORD>& st,
+                                           R theta, R* k)
 {
-    constexpr int NN = Stencil<DIM, R>::NN;
+    constexpr int NN = Stencil<DIM, R, ORD>::NN;
     R ua[DIM], ub[DIM];
 #pragma unroll
     for (int i = 0; i < DIM; ++i) {
@@ -439,12 +511,12 @@ __device__ __forceinline__ void gather_vel(const TraceArgs<T>& A, uint32_t mbase
     for (int q = 0; q < NN; ++q) {
         const uint32_t slot = mbase + (uint32_t)st.idx[q];
         T a[DIM];
-        load_vec<DIM, T>(A, 0, slot, a);
+        load_vec<DIM, T>(Lv.ea, Lv.eb, slot, a);
 #pragma unroll
         for (int i = 0; i < DIM; ++i) ua[i] = fma(st.phi[q], (R)a[i], ua[i]);
         if constexpr (NLEV == 2) {
             T b[DIM];
-            load_vec<DIM, T>(A, 1, slot, b);
+            load_vec<DIM, T>(Lv.la, Lv.lb, slot, b);
 #pragma unroll
             for (int i = 0; i < DIM; ++i) ub[i] = fma(st.phi[q], (R)b[i], ub[i]);
         }
@@ -456,13 +528,13 @@ __device__ __forceinline__ void gather_vel(const TraceArgs<T>& A, uint32_t mbase
 // velocity at a lattice node: the nodal values (P2 interpolation is the
 // identity there)
 template <int DIM, int NLEV, typename T, typename R>
-__device__ __forceinline__ void nodal_vel(const TraceArgs<T>& A, uint32_t slot, R theta, R* k)
+__device__ __forceinline__ void nodal_vel(const Levels<T>& Lv, uint32_t slot, R theta, R* k)
 {
     T a[DIM];
-    load_vec<DIM, T>(A, 0, slot, a);
+    load_vec<DIM, T>(Lv.ea, Lv.eb, slot, a);
     if constexpr (NLEV == 2) {
         T b[DIM];
-        load_vec<DIM, T>(A, 1, slot, b);
+        load_vec<DIM, T>(Lv.la, Lv.lb, slot, b);
 #pragma unroll
         for (int i = 0; i < DIM; ++i) k[i] = (R(1) - theta) * (R)a[i] + theta * (R)b[i];
     } else {
@@ -471,10 +543,10 @@ __device__ __forceinline__ void nodal_vel(const TraceArgs<T>& A, uint32_t slot, 
     }
 }
 
-template <int DIM, typename T, typename R>
-__device__ __forceinline__ R gather_scalar(const TraceArgs<T>& A, uint32_t mbase, const Stencil<DIM, R>& st)
+template <int DIM, typename T, typename R, int ORD>
+__device__ __forceinline__ R gather_scalar(const TraceArgs<T>& A, uint32_t mbase, const Stencil<DIM, R, ORD>& st)
 {
-    constexpr int NN = Stencil<DIM, R>::NN;
+    constexpr int NN = Stencil<DIM, R, ORD>::NN;
     R acc = R(0);
 #pragma unroll
     for (int q = 0; q < NN; ++q)
@@ -533,9 +605,14 @@ __device__ __forceinline__ unsigned long long wave_append(unsigned long long* le
 
 // --------------------------------------------------------------- fp64 trace
 
-template <int DIM, int NLEV, int BLEND>
+// T is the storage type of the fields: double (MMOC_FP64) or float
+// (MMOC_FP32_FIELDS: float32 records, float64 arithmetic throughout).
+// GENERIC: a general explicit Runge-Kutta method from A.rk (the paper uses
+// RK4 and notes that any explicit RK method applies, Sec. 3.1); otherwise the
+// classical RK4 with its weights folded into the code.
+template <int DIM, int NLEV, int BLEND, typename T, bool GENERIC, int ORD>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP64)))
-void trace_fp64_kernel(const TraceArgs<double> A, const MacroGeo* __restrict__ geo, double* __restrict__ c_hat,
+void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T* __restrict__ c_hat,
                        double* __restrict__ X, unsigned long long* __restrict__ stats)
 {
     const int64_t t = logical_block() * kTB + threadIdx.x;
@@ -546,7 +623,7 @@ void trace_fp64_kernel(const TraceArgs<double> A, const MacroGeo* __restrict__ g
         const uint64_t e = A.owned[pid];
         int M;
         double Y[DIM];
-        dof_position<DIM, BLEND>(geo, e, A.level_n, M, Y);
+        dof_position<DIM, BLEND>(geo, e, A.lat_m, M, Y);
         uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
         const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
         const double h = A.dt / (double)A.substeps;
@@ -554,46 +631,87 @@ void trace_fp64_kernel(const TraceArgs<double> A, const MacroGeo* __restrict__ g
         const double h6 = h / 6.0;
         const double invS = 1.0 / (double)A.substeps;
         double s[DIM], l0, lmin;
-        Stencil<DIM, double> st;
+        Stencil<DIM, double, ORD> st;
+        // velocity at stage point y and stage time theta (Sec. 2.3.2: walk
+        // from the previous macro, micro element, P2 sums of both levels)
+        auto velocity = [&](const double* y, const Levels<T>& Lv, double theta, double* k) {
+            l0 = ref_at<DIM, BLEND>(geo, M, y, s);
+            lmin = lam_min<DIM, double>(l0, s);
+            if (lmin < -A.eps_in) {
+                const unsigned r = walk64<DIM, BLEND>(geo, A.nm, A.max_hops, A.eps_in, M, y[0], y[1],
+                                                     DIM == 3 ? y[DIM - 1] : 0.0);
+                flags |= r >> 27;
+                M = (int)(r & ((1u << 27) - 1));
+                mbase = (uint32_t)M * (uint32_t)A.npm;
+                l0 = ref_at<DIM, BLEND>(geo, M, y, s);
+                lmin = lam_min<DIM, double>(l0, s);
+            }
+            micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
+            gather_vel<DIM, NLEV, T, double>(Lv, mbase, st, theta, k);
+        };
+        const int nsub = A.substeps * A.n_int;
+        if constexpr (GENERIC) {
 #pragma unroll 1
-        for (int j = 0; j < A.substeps; ++j) {
-            double ks[DIM], acc[DIM], y[DIM];
+            for (int j = 0; j < nsub; ++j) {
+                double K[kMaxStages][DIM];
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) y[i] = Y[i];
-#pragma unroll 1
-            for (int stg = 0; stg < 4; ++stg) {
-                // stage time theta = 1 - (j + a_s)/S, a_s = 0, 1/2, 1/2, 1
-                const double as = stg == 0 ? 0.0 : (stg == 3 ? 1.0 : 0.5);
-                const double theta = 1.0 - ((double)j + as) * invS;
-                if (j == 0 && stg == 0) {
-                    // the particle sits on its own DoF
-                    nodal_vel<DIM, NLEV, double, double>(A, own_slot, theta, ks);
-                } else {
-                    l0 = ref_at<DIM, BLEND>(geo, M, y, s);
-                    lmin = lam_min<DIM, double>(l0, s);
-                    if (lmin < -A.eps_in) {
-                        const unsigned r = walk64<DIM, BLEND>(geo, A.nm, A.max_hops, A.eps_in, M, y[0], y[1],
-                                                             DIM == 3 ? y[DIM - 1] : 0.0);
-                        flags |= r >> 27;
-                        M = (int)(r & ((1u << 27) - 1));
-                        mbase = (uint32_t)M * (uint32_t)A.npm;
-                        l0 = ref_at<DIM, BLEND>(geo, M, y, s);
-                        lmin = lam_min<DIM, double>(l0, s);
+                for (int q = 0; q < kMaxStages; ++q) {
+                    if (q < A.rk.s) {
+                        // y_q = Y - h sum_{l<q} a_ql k_l at theta = 1 - (j + c_q)/S
+                        double y[DIM];
+#pragma unroll
+                        for (int i = 0; i < DIM; ++i) {
+                            double sum = 0.0;
+#pragma unroll
+                            for (int l = 0; l < q; ++l) sum = fma(A.rk.a[q * kMaxStages + l], K[l][i], sum);
+                            y[i] = Y[i] - h * sum;
+                        }
+                        double theta;
+                        const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)j + A.rk.c[q]) * invS, theta);
+                        if (j == 0 && q == 0) nodal_vel<DIM, NLEV, T, double>(Lv, own_slot, theta, K[0]);
+                        else velocity(y, Lv, theta, K[q]);
                     }
-                    micro<DIM, double>(s, l0, lmin, A.level_n, st);
-                    gather_vel<DIM, NLEV, double, double>(A, mbase, st, theta, ks);
                 }
-                // k1 + 2 k2 + 2 k3 + k4 accumulated in stage order; next stage point
-                const double wst = (stg == 0 || stg == 3) ? 1.0 : 2.0;
-                const double cnext = stg == 2 ? h : hh;
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) {
-                    acc[i] = stg == 0 ? ks[i] : fma(wst, ks[i], acc[i]);
-                    y[i] = Y[i] - cnext * ks[i];
+                    double sum = 0.0;
+#pragma unroll
+                    for (int q = 0; q < kMaxStages; ++q)
+                        if (q < A.rk.s) sum = fma(A.rk.b[q], K[q][i], sum);
+                    Y[i] = Y[i] - h * sum;
                 }
             }
+        } else {
+#pragma unroll 1
+            for (int j = 0; j < nsub; ++j) {
+                double ks[DIM], acc[DIM], y[DIM];
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - h6 * acc[i];
+                for (int i = 0; i < DIM; ++i) y[i] = Y[i];
+#pragma unroll 1
+                for (int stg = 0; stg < 4; ++stg) {
+                    // stage (j + a_s)/S intervals back, a_s = 0, 1/2, 1/2, 1; one
+                    // interval: theta = 1 - (j + a_s)/S
+                    const double as = stg == 0 ? 0.0 : (stg == 3 ? 1.0 : 0.5);
+                    double theta;
+                    const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)j + as) * invS, theta);
+                    if (j == 0 && stg == 0) {
+                        // the particle sits on its own DoF
+                        nodal_vel<DIM, NLEV, T, double>(Lv, own_slot, theta, ks);
+                    } else {
+                        velocity(y, Lv, theta, ks);
+                    }
+                    // k1 + 2 k2 + 2 k3 + k4 accumulated in stage order; next stage point
+                    const double wst = (stg == 0 || stg == 3) ? 1.0 : 2.0;
+                    const double cnext = stg == 2 ? h : hh;
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) {
+                        acc[i] = stg == 0 ? ks[i] : fma(wst, ks[i], acc[i]);
+                        y[i] = Y[i] - cnext * ks[i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - h6 * acc[i];
+            }
         }
         // step (iii): the scalar at the departure point
         l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
@@ -607,13 +725,13 @@ void trace_fp64_kernel(const TraceArgs<double> A, const MacroGeo* __restrict__ g
             l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
             lmin = lam_min<DIM, double>(l0, s);
         }
-        micro<DIM, double>(s, l0, lmin, A.level_n, st);
-        const double v = gather_scalar<DIM, double, double>(A, mbase, st);
+        micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
+        const double v = gather_scalar<DIM, T, double>(A, mbase, st);
         bool bad = v != v;
 #pragma unroll
         for (int i = 0; i < DIM; ++i) bad |= Y[i] != Y[i];
         if (bad) flags |= LF_NAN;
-        if (c_hat) c_hat[pid] = v;
+        if (c_hat) c_hat[pid] = (T)v;
         if (X) {
 #pragma unroll
             for (int i = 0; i < DIM; ++i) X[(int64_t)i * A.xstride + pid] = Y[i];
@@ -641,9 +759,8 @@ struct Geo32 {
 #pragma unroll
             for (int c = 0; c < DIM; ++c) bi[r][c] = g[M].binvf[r * 3 + c];
         if constexpr (BLEND) {
-            pn[0] = g[M].pn[0];
-            pn[1] = g[M].pn[1];
-            pn[2] = g[M].pn[2];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) pn[i] = g[M].pn[i];
             pc = g[M].pc;
         }
     }
@@ -655,8 +772,8 @@ struct Geo32 {
     {
         float p[DIM];
         if constexpr (BLEND) {
-            const double nz = pn[0] * y[0] + pn[1] * y[1] + pn[2] * y[2];
-            const double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+            const double nz = dotd<DIM>(pn, y);
+            const double r = sqrt(dotd<DIM>(y, y));
             const double f = pc * r / nz;
 #pragma unroll
             for (int i = 0; i < DIM; ++i) p[i] = (float)fma(y[i], f, -v0[i]);
@@ -699,10 +816,10 @@ __device__ __forceinline__ float ref32_at(const MacroGeo* __restrict__ geo, int 
 // float64 (a macro tie or a macro change), then the micro element in float64
 // (shape functions handed back in float32).  Out of line: it runs for a
 // small fraction of the evaluations and must not cost the hot loop registers.
-template <int DIM, int BLEND>
+template <int DIM, int BLEND, int ORD>
 __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int nm, int max_hops, double eps, int M,
                                           int level_n, int walk, double y0, double y1, double y2,
-                                          Stencil<DIM, float>* out)
+                                          Stencil<DIM, float, ORD>* out)
 {
     unsigned r = (unsigned)M;
     if (walk) r = walk64<DIM, BLEND>(geo, nm, max_hops, eps, M, y0, y1, y2);
@@ -713,10 +830,10 @@ __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int 
     double s[DIM];
     const double l0 = G.ref(y, s);
     const double lmin = lam_min<DIM, double>(l0, s);
-    Stencil<DIM, double> st;
-    micro<DIM, double>(s, l0, lmin, level_n, st);
+    Stencil<DIM, double, ORD> st;
+    micro<DIM, double, false, ORD>(s, l0, lmin, level_n, st);
 #pragma unroll
-    for (int q = 0; q < Stencil<DIM, double>::NN; ++q) {
+    for (int q = 0; q < Stencil<DIM, double, ORD>::NN; ++q) {
         out->idx[q] = st.idx[q];
         out->phi[q] = (float)st.phi[q];
     }
@@ -729,9 +846,9 @@ __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int 
 // in float64, and so is a micro decision within eps32_micro * n of a tie.
 // Near a boundary face there is no second macro to choose: the point stays,
 // and its element is selected from the clamped barycentrics as in float64.
-template <int DIM, int BLEND>
+template <int DIM, int BLEND, int ORD>
 __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint32_t& mbase, const double* y,
-                                         Stencil<DIM, float>& st, unsigned& flags)
+                                         Stencil<DIM, float, ORD>& st, unsigned& flags)
 {
     float s[DIM];
     const float l0 = ref32_at<DIM, BLEND>(A.geo, M, y, s);
@@ -751,16 +868,16 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint
     bool redo = macro_redo;
     if (!macro_redo) {
         if (A.eps32_micro > 0.0f) {
-            const float gap = micro<DIM, float, true>(s, l0, lmin, A.level_n, st);
+            const float gap = micro<DIM, float, true, ORD>(s, l0, lmin, A.level_n, st);
             redo = gap < A.eps32_micro * (float)A.level_n;
         } else {
-            micro<DIM, float>(s, l0, lmin, A.level_n, st);
+            micro<DIM, float, false, ORD>(s, l0, lmin, A.level_n, st);
         }
     }
     if (redo) {
         if (!macro_redo || lmin > -A.eps32_macro) flags |= LF_TIEBAND;
-        Stencil<DIM, float> s64;
-        const unsigned r = locate64<DIM, BLEND>(A.geo, A.nm, A.max_hops, A.eps_in, M, A.level_n, macro_redo, y[0],
+        Stencil<DIM, float, ORD> s64;
+        const unsigned r = locate64<DIM, BLEND, ORD>(A.geo, A.nm, A.max_hops, A.eps_in, M, A.level_n, macro_redo, y[0],
                                                 y[1], DIM == 3 ? y[DIM - 1] : 0.0, &s64);
         flags |= r >> 27;
         M = (int)(r & ((1u << 27) - 1));
@@ -769,7 +886,7 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint
     }
 }
 
-template <int DIM, int NLEV, int BLEND>
+template <int DIM, int NLEV, int BLEND, int ORD>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP32)))
 void trace_fp32_kernel(const TraceArgs<float> A)
 {
@@ -781,30 +898,32 @@ void trace_fp32_kernel(const TraceArgs<float> A)
         const uint64_t e = A.owned[pid];
         int M;
         double Y[DIM];
-        dof_position<DIM, BLEND>(A.geo, e, A.level_n, M, Y);
+        dof_position<DIM, BLEND>(A.geo, e, A.lat_m, M, Y);
         uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
         const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
         const double hd = A.dt / (double)A.substeps;
         const float h = (float)hd;
         const float hh = 0.5f * h;
         const float h6 = h / 6.0f;
-        const float invS = 1.0f / (float)A.substeps;
-        Stencil<DIM, float> st;
+        const double invSd = 1.0 / (double)A.substeps;
+        Stencil<DIM, float, ORD> st;
+        const int nsub = A.substeps * A.n_int;
 #pragma unroll 1
-        for (int j = 0; j < A.substeps; ++j) {
+        for (int j = 0; j < nsub; ++j) {
             float ks[DIM], acc[DIM];
             double y[DIM];
 #pragma unroll
             for (int i = 0; i < DIM; ++i) y[i] = Y[i];
 #pragma unroll 1
             for (int stg = 0; stg < 4; ++stg) {
-                const float as = stg == 0 ? 0.0f : (stg == 3 ? 1.0f : 0.5f);
-                const float theta = 1.0f - ((float)j + as) * invS;
+                const double as = stg == 0 ? 0.0 : (stg == 3 ? 1.0 : 0.5);
+                float theta;
+                const Levels<float> Lv = levels_at<NLEV, float, float>(A, ((double)j + as) * invSd, theta);
                 if (j == 0 && stg == 0) {
-                    nodal_vel<DIM, NLEV, float, float>(A, own_slot, theta, ks);
+                    nodal_vel<DIM, NLEV, float, float>(Lv, own_slot, theta, ks);
                 } else {
-                    locate32<DIM, BLEND>(A, M, mbase, y, st, flags);
-                    gather_vel<DIM, NLEV, float, float>(A, mbase, st, theta, ks);
+                    locate32<DIM, BLEND, ORD>(A, M, mbase, y, st, flags);
+                    gather_vel<DIM, NLEV, float, float>(Lv, mbase, st, theta, ks);
                 }
                 const float wst = (stg == 0 || stg == 3) ? 1.0f : 2.0f;
                 const float cnext = stg == 2 ? h : hh;
@@ -818,7 +937,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
 #pragma unroll
             for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - (double)(h6 * acc[i]);
         }
-        locate32<DIM, BLEND>(A, M, mbase, Y, st, flags);
+        locate32<DIM, BLEND, ORD>(A, M, mbase, Y, st, flags);
         const float v = gather_scalar<DIM, float, float>(A, mbase, st);
         bool bad = v != v;
 #pragma unroll
@@ -837,8 +956,8 @@ void trace_fp32_kernel(const TraceArgs<float> A)
 
 // chat_i = c_h^n(X_i) for departure points produced elsewhere (the
 // surrogate): the walk starts in the particle's own macro.
-template <int DIM, int BLEND>
-__global__ __launch_bounds__(kTB) void scalar_eval_fp64_kernel(const TraceArgs<double> A)
+template <int DIM, int BLEND, typename T, int ORD>
+__global__ __launch_bounds__(kTB) void scalar_eval_fp64_kernel(const TraceArgs<T> A)
 {
     const int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x;
     const bool active = t < A.n;
@@ -859,16 +978,16 @@ __global__ __launch_bounds__(kTB) void scalar_eval_fp64_kernel(const TraceArgs<d
             l0 = ref_at<DIM, BLEND>(A.geo, M, Y, s);
             lmin = lam_min<DIM, double>(l0, s);
         }
-        Stencil<DIM, double> st;
-        micro<DIM, double>(s, l0, lmin, A.level_n, st);
-        const double v = gather_scalar<DIM, double, double>(A, (uint32_t)M * (uint32_t)A.npm, st);
+        Stencil<DIM, double, ORD> st;
+        micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
+        const double v = gather_scalar<DIM, T, double>(A, (uint32_t)M * (uint32_t)A.npm, st);
         if (v != v) flags |= LF_NAN;
-        A.c_hat[t] = v;
+        A.c_hat[t] = (T)v;
     }
     (void)flags;
 }
 
-template <int DIM, int BLEND>
+template <int DIM, int BLEND, int ORD>
 __global__ __launch_bounds__(kTB) void scalar_eval_fp32_kernel(const TraceArgs<float> A)
 {
     const int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x;
@@ -878,9 +997,9 @@ __global__ __launch_bounds__(kTB) void scalar_eval_fp32_kernel(const TraceArgs<f
 #pragma unroll
     for (int i = 0; i < DIM; ++i) Y[i] = A.X[(int64_t)i * A.xstride + t];
     uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
-    Stencil<DIM, float> st;
+    Stencil<DIM, float, ORD> st;
     unsigned flags = 0;
-    locate32<DIM, BLEND>(A, M, mbase, Y, st, flags);
+    locate32<DIM, BLEND, ORD>(A, M, mbase, Y, st, flags);
     A.c_hat[t] = gather_scalar<DIM, float, float>(A, mbase, st);
 }
 
@@ -976,57 +1095,102 @@ __global__ __launch_bounds__(256) void fallback_list_kernel(int64_t n, int tile,
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(stat_word(stats, ST_FALLBACK), cnt);
 }
 
+// grid of the remapped kernels: a whole number of XCD rounds (the blocks
+// beyond the particle range have no active lane)
 inline unsigned grid_xcd(int64_t n)
 {
+    constexpr int64_t round = 8 * (MMOC_XCD_CHUNK > 0 ? MMOC_XCD_CHUNK : 1);
     int64_t b = (n + kTB - 1) / kTB;
-    b = (b + 7) / 8 * 8;
+    b = (b + round - 1) / round * round;
     return (unsigned)b;
 }
 
 }  // namespace
 
-hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s)
+template <typename T, bool G, int ORD>
+hipError_t launch_trace_f64g(int dim, int blend, const TraceArgs<T>& a, hipStream_t s)
 {
-    if (a.n <= 0) return hipSuccess;
     const dim3 grid(grid_xcd(a.n)), block(kTB);
     const bool st = a.nlev == 1;
     if (dim == 2 && !blend) {
-        if (st) trace_fp64_kernel<2, 1, 0><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
-        else trace_fp64_kernel<2, 2, 0><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        if (st) trace_fp64_kernel<2, 1, 0, T, G, ORD><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        else trace_fp64_kernel<2, 2, 0, T, G, ORD><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
     } else if (dim == 3 && !blend) {
-        if (st) trace_fp64_kernel<3, 1, 0><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
-        else trace_fp64_kernel<3, 2, 0><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
-    } else if (dim == 3 && blend) {
-        if (st) trace_fp64_kernel<3, 1, 1><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
-        else trace_fp64_kernel<3, 2, 1><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        if (st) trace_fp64_kernel<3, 1, 0, T, G, ORD><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        else trace_fp64_kernel<3, 2, 0, T, G, ORD><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+    } else if (dim == 3 && blend && ORD == 2) {
+        if (st) trace_fp64_kernel<3, 1, 1, T, G, 2><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        else trace_fp64_kernel<3, 2, 1, T, G, 2><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+    } else if (dim == 2 && blend && ORD == 2) {
+        if (st) trace_fp64_kernel<2, 1, 1, T, G, 2><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+        else trace_fp64_kernel<2, 2, 1, T, G, 2><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
     } else {
         return hipErrorNotSupported;
     }
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_trace_f64(int dim, int blend, const TraceArgs<T>& a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    if (a.ord == 1)
+        return a.rk.s > 0 ? launch_trace_f64g<T, true, 1>(dim, blend, a, s)
+                          : launch_trace_f64g<T, false, 1>(dim, blend, a, s);
+    return a.rk.s > 0 ? launch_trace_f64g<T, true, 2>(dim, blend, a, s)
+                      : launch_trace_f64g<T, false, 2>(dim, blend, a, s);
+}
+
+hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s)
+{
+    return launch_trace_f64(dim, blend, a, s);
+}
+
+hipError_t launch_trace_fp32_fields(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
+{
+    return launch_trace_f64(dim, blend, a, s);
+}
+
 template <typename T, typename K2, typename K3, typename K3b>
-hipError_t launch_plain(int dim, int blend, const T& a, hipStream_t s, K2 k2, K3 k3, K3b k3b)
+hipError_t launch_plain(int dim, int blend, const T& a, hipStream_t s, K2 k2, K3 k3, K2 k2b, K3b k3b)
 {
     if (a.n <= 0) return hipSuccess;
     const dim3 grid((unsigned)((a.n + kTB - 1) / kTB)), block(kTB);
     if (dim == 2 && !blend) k2<<<grid, block, 0, s>>>(a);
     else if (dim == 3 && !blend) k3<<<grid, block, 0, s>>>(a);
-    else if (dim == 3 && blend) k3b<<<grid, block, 0, s>>>(a);
+    else if (dim == 2 && blend && k2b) k2b<<<grid, block, 0, s>>>(a);
+    else if (dim == 3 && blend && k3b) k3b<<<grid, block, 0, s>>>(a);
     else return hipErrorNotSupported;
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_scalar_eval_f64(int dim, int blend, const TraceArgs<T>& a, hipStream_t s)
+{
+    if (a.ord == 1)
+        return launch_plain(dim, blend, a, s, scalar_eval_fp64_kernel<2, 0, T, 1>, scalar_eval_fp64_kernel<3, 0, T, 1>,
+                            (void (*)(TraceArgs<T>)) nullptr, (void (*)(TraceArgs<T>)) nullptr);
+    return launch_plain(dim, blend, a, s, scalar_eval_fp64_kernel<2, 0, T, 2>, scalar_eval_fp64_kernel<3, 0, T, 2>,
+                        scalar_eval_fp64_kernel<2, 1, T, 2>, scalar_eval_fp64_kernel<3, 1, T, 2>);
+}
+
 hipError_t launch_scalar_eval_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s)
 {
-    return launch_plain(dim, blend, a, s, scalar_eval_fp64_kernel<2, 0>, scalar_eval_fp64_kernel<3, 0>,
-                        scalar_eval_fp64_kernel<3, 1>);
+    return launch_scalar_eval_f64(dim, blend, a, s);
+}
+
+hipError_t launch_scalar_eval_fp32_fields(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
+{
+    return launch_scalar_eval_f64(dim, blend, a, s);
 }
 
 hipError_t launch_scalar_eval_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
 {
-    return launch_plain(dim, blend, a, s, scalar_eval_fp32_kernel<2, 0>, scalar_eval_fp32_kernel<3, 0>,
-                        scalar_eval_fp32_kernel<3, 1>);
+    if (a.ord == 1)
+        return launch_plain(dim, blend, a, s, scalar_eval_fp32_kernel<2, 0, 1>, scalar_eval_fp32_kernel<3, 0, 1>,
+                            (void (*)(TraceArgs<float>)) nullptr, (void (*)(TraceArgs<float>)) nullptr);
+    return launch_plain(dim, blend, a, s, scalar_eval_fp32_kernel<2, 0, 2>, scalar_eval_fp32_kernel<3, 0, 2>,
+                        scalar_eval_fp32_kernel<2, 1, 2>, scalar_eval_fp32_kernel<3, 1, 2>);
 }
 
 namespace mlp {
@@ -1062,24 +1226,33 @@ hipError_t launch_fallback_list(int64_t n, int tile, const unsigned char* tile_f
 
 }  // namespace mlp
 
-hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
+template <int ORD>
+hipError_t launch_trace_fp32o(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
 {
-    if (a.n <= 0) return hipSuccess;
     const dim3 grid(grid_xcd(a.n)), block(kTB);
     const bool st = a.nlev == 1;
     if (dim == 2 && !blend) {
-        if (st) trace_fp32_kernel<2, 1, 0><<<grid, block, 0, s>>>(a);
-        else trace_fp32_kernel<2, 2, 0><<<grid, block, 0, s>>>(a);
+        if (st) trace_fp32_kernel<2, 1, 0, ORD><<<grid, block, 0, s>>>(a);
+        else trace_fp32_kernel<2, 2, 0, ORD><<<grid, block, 0, s>>>(a);
     } else if (dim == 3 && !blend) {
-        if (st) trace_fp32_kernel<3, 1, 0><<<grid, block, 0, s>>>(a);
-        else trace_fp32_kernel<3, 2, 0><<<grid, block, 0, s>>>(a);
-    } else if (dim == 3 && blend) {
-        if (st) trace_fp32_kernel<3, 1, 1><<<grid, block, 0, s>>>(a);
-        else trace_fp32_kernel<3, 2, 1><<<grid, block, 0, s>>>(a);
+        if (st) trace_fp32_kernel<3, 1, 0, ORD><<<grid, block, 0, s>>>(a);
+        else trace_fp32_kernel<3, 2, 0, ORD><<<grid, block, 0, s>>>(a);
+    } else if (dim == 3 && blend && ORD == 2) {
+        if (st) trace_fp32_kernel<3, 1, 1, 2><<<grid, block, 0, s>>>(a);
+        else trace_fp32_kernel<3, 2, 1, 2><<<grid, block, 0, s>>>(a);
+    } else if (dim == 2 && blend && ORD == 2) {
+        if (st) trace_fp32_kernel<2, 1, 1, 2><<<grid, block, 0, s>>>(a);
+        else trace_fp32_kernel<2, 2, 1, 2><<<grid, block, 0, s>>>(a);
     } else {
         return hipErrorNotSupported;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    return a.ord == 1 ? launch_trace_fp32o<1>(dim, blend, a, s) : launch_trace_fp32o<2>(dim, blend, a, s);
 }
 
 }  // namespace mmoc

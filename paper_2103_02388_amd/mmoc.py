@@ -20,6 +20,7 @@ from .build import LIB
 
 MMOC_FP64 = 0
 MMOC_FP32_MIXED = 1
+MMOC_FP32_FIELDS = 2
 MMOC_BLEND_NONE = 0
 MMOC_BLEND_SHELL_RADIAL = 1
 
@@ -33,7 +34,7 @@ EXPORTED = [
     "mmoc_mlp_configure", "mmoc_mlp_record", "mmoc_mlp_train", "mmoc_mlp_get_weights",
     "mmoc_mlp_set_weights", "mmoc_mlp_infer", "mmoc_trace_step_surrogate", "mmoc_last_error",
     "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad", "mmoc_mass_inner", "mmoc_field_range",
-    "mmoc_lookback_run",
+    "mmoc_lookback_run", "mmoc_set_rk_tableau", "mmoc_cfl_time_step", "mmoc_set_level_count", "mmoc_trace_span",
 ]
 
 
@@ -45,7 +46,7 @@ class MMOCError(RuntimeError):
 
 class mmoc_options(C.Structure):
     _fields_ = [("eps_in", C.c_double), ("eps32_macro", C.c_float), ("eps32_micro", C.c_float),
-                ("max_hops", C.c_int), ("reserved", C.c_int * 4)]
+                ("max_hops", C.c_int), ("order", C.c_int), ("reserved", C.c_int * 3)]
 
 
 class mmoc_stats(C.Structure):
@@ -97,6 +98,10 @@ def lib():
         "mmoc_mass_inner": (st, [P, P, P, P, P, C.POINTER(D)]),
         "mmoc_field_range": (st, [P, P, C.POINTER(D), C.POINTER(D)]),
         "mmoc_lookback_run": (st, [P, D, I, I64, I64, P, I64, P]),
+        "mmoc_set_rk_tableau": (st, [P, I, P, P, P]),
+        "mmoc_cfl_time_step": (st, [P, D, I, C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
+        "mmoc_set_level_count": (st, [P, I]),
+        "mmoc_trace_span": (st, [P, I, I, D, I, P, P]),
         "mmoc_last_error": (C.c_char_p, [P]),
         "mmoc_destroy": (None, [P]),
     }
@@ -266,6 +271,33 @@ def mmoc_lookback_run(ctx, tau, substeps, n_steps, b, ring: torch.Tensor, c_out:
                                         int(ring.shape[0]), _ptr(c_out)))
 
 
+def mmoc_set_rk_tableau(ctx, A=None, b=None, c=None):
+    """A general explicit RK method (A [s][s], b [s], c [s]); None restores RK4."""
+    if A is None:
+        _check(ctx, lib().mmoc_set_rk_tableau(ctx, 0, None, None, None))
+        return
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    dp = lambda x: x.ctypes.data_as(C.c_void_p)
+    _check(ctx, lib().mmoc_set_rk_tableau(ctx, int(b.shape[0]), dp(A), dp(b), dp(c)))
+
+
+def mmoc_cfl_time_step(ctx, cfl, level=0):
+    """(tau, max |u|, h_min)."""
+    t, u, h = C.c_double(), C.c_double(), C.c_double()
+    _check(ctx, lib().mmoc_cfl_time_step(ctx, float(cfl), int(level), C.byref(t), C.byref(u), C.byref(h)))
+    return t.value, u.value, h.value
+
+
+def mmoc_set_level_count(ctx, levels):
+    _check(ctx, lib().mmoc_set_level_count(ctx, int(levels)))
+
+
+def mmoc_trace_span(ctx, first, n_int, dt, substeps, c_hat: torch.Tensor, X: Optional[torch.Tensor]):
+    _check(ctx, lib().mmoc_trace_span(ctx, int(first), int(n_int), float(dt), int(substeps), _ptr(c_hat), _ptr(X)))
+
+
 def mmoc_last_error(ctx):
     return lib().mmoc_last_error(ctx).decode()
 
@@ -292,7 +324,12 @@ class Tracer:
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
-    def from_workload(cls, wl, precision=MMOC_FP64, level=None, options=None):
+    def from_workload(cls, wl, precision=MMOC_FP64, level=None, options=None, order=None):
+        """order: 2 (P2, default) or 1 (P1); sets options.order."""
+        if order is not None:
+            if options is None:
+                options = mmoc_default_options()
+            options.order = int(order)
         return cls(wl.dim, wl.level if level is None else level, wl.vertices, wl.macros, wl.blend, precision,
                    options)
 
@@ -341,6 +378,17 @@ class Tracer:
 
     def reset_stats(self):
         mmoc_reset_stats(self.ctx)
+
+    def set_level_count(self, levels):
+        mmoc_set_level_count(self.ctx, levels)
+
+    def trace_span(self, first, n_int, dt, substeps, c_hat=None, X=None, want_X=True):
+        if c_hat is None:
+            c_hat = torch.empty(self.N, dtype=self.scalar_dtype, device=self.device)
+        if X is None and want_X:
+            X = torch.empty((self.dim, self.N), dtype=torch.float64, device=self.device)
+        mmoc_trace_span(self.ctx, first, n_int, dt, substeps, c_hat, X)
+        return c_hat, X
 
     def mass_inner(self, a=None, a_sub=None, b=None, b_sub=None):
         """(a - a_sub)^T M (b - b_sub) with the P2 mass matrix (None: ones / zero)."""

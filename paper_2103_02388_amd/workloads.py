@@ -15,6 +15,8 @@ The shapes follow the paper's benchmarks (Sec. 3 and 4):
   field u = (0.5 - y, x - 0.5).
 * ``cube6``    -- unit cube split into the six Kuhn tetrahedra, used with the
   LeVeque swirl field of Sec. 3.3 and with the rising-plume field.
+* ``annulus``  -- annulus r in [0.5, 1.5] of 6 x 2 quadrilateral cells cut
+  into triangles (Sec. 4, advection-diffusion), with radial blending.
 * ``shell``    -- thick spherical shell: a subdivided icosahedron extruded into
   radial layers, each prism split into three tetrahedra (Sec. 5.3 uses a
   shell of tetrahedral macro cells projected onto the sphere).
@@ -135,6 +137,33 @@ def shell(subdiv: int = 4, layers: int = 4, r_min: float = 0.55, r_max: float = 
     return verts, np.array(macros, dtype=np.int32)
 
 
+def annulus(n_ang: int = 6, n_rad: int = 2, r_min: float = 0.5, r_max: float = 1.5):
+    """Annulus r in [r_min, r_max] as triangles (Sec. 4: a coarse triangular
+    mesh refined uniformly and projected onto the annulus).
+
+    ``n_ang`` sectors times ``n_rad`` radial layers of quadrilateral cells,
+    each cut along the diagonal through its smallest vertex id; vertex id =
+    layer * n_ang + sector, vertex (r_j cos phi_k, r_j sin phi_k) with
+    phi_k = 2 pi k / n_ang.  Each triangle lists its vertices in ascending
+    id.  The flat mesh is mapped onto the round annulus by the caller's
+    blending map.
+    """
+    radii = np.linspace(r_min, r_max, n_rad + 1)
+    ang = 2.0 * np.pi * np.arange(n_ang) / n_ang
+    verts = np.array([[r * math.cos(a), r * math.sin(a)] for r in radii for a in ang])
+    tris = []
+    for j in range(n_rad):
+        for k in range(n_ang):
+            a, b = j * n_ang + k, j * n_ang + (k + 1) % n_ang
+            c, d = a + n_ang, b + n_ang
+            lo = min(a, b, c, d)
+            opp = {a: d, b: c, c: b, d: a}[lo]  # the diagonal through the smallest id
+            rest = [v for v in (a, b, c, d) if v not in (lo, opp)]
+            for v in rest:
+                tris.append(sorted((lo, opp, v)))
+    return verts, np.array(tris, dtype=np.int32)
+
+
 # ---------------------------------------------------------------------------
 # analytic fields (torch, float64, any device)
 # ---------------------------------------------------------------------------
@@ -199,6 +228,35 @@ def swirl_velocity(x: torch.Tensor, t: float) -> torch.Tensor:
     s2x, s2y, s2z = torch.sin(px) ** 2, torch.sin(py) ** 2, torch.sin(pz) ** 2
     sx, sy, sz = torch.sin(2 * px), torch.sin(2 * py), torch.sin(2 * pz)
     return torch.stack([2.0 * s2x * sy * sz * g, -sx * s2y * sz * g, -sx * sy * s2z * g], dim=1)
+
+
+def circular_velocity(x: torch.Tensor, t: float = 0.0) -> torch.Tensor:
+    """Rotation about the origin, u = (-x2, x1) (Sec. 4, annulus)."""
+    return torch.stack([-x[:, 1], x[:, 0]], dim=1)
+
+
+class MovingGaussian:
+    """Smeared Gaussian hill of the advection-diffusion benchmark (Sec. 4):
+    c(x, t) = exp(-|x - xhat(t)|^2 / (4 t kappa)) / (4 pi t kappa), the
+    centre xhat(t) = (xb1 cos t - xb2 sin t, -xb1 sin t + xb2 cos t) with
+    xb = (0, 1), which the field u = (-x2, x1) carries.  The run starts at
+    t0 = 2 pi 1e-3 / kappa, so that the initial shape does not depend on
+    kappa, and ends after one revolution at t0 + 2 pi."""
+
+    def __init__(self, kappa: float, xbar=(0.0, 1.0)):
+        self.kappa = float(kappa)
+        self.xbar = (float(xbar[0]), float(xbar[1]))
+        self.t0 = 2.0 * math.pi * 1e-3 / self.kappa
+
+    def centre(self, t: float):
+        x1, x2 = self.xbar
+        return (x1 * math.cos(t) - x2 * math.sin(t), -x1 * math.sin(t) + x2 * math.cos(t))
+
+    def __call__(self, x: torch.Tensor, t: float) -> torch.Tensor:
+        c1, c2 = self.centre(t)
+        r2 = (x[:, 0] - c1) ** 2 + (x[:, 1] - c2) ** 2
+        s = 4.0 * t * self.kappa
+        return torch.exp(-r2 / s) / (math.pi * s)
 
 
 def two_blobs(x: torch.Tensor) -> torch.Tensor:
@@ -386,7 +444,7 @@ class Workload:
     level: int
     vertices: np.ndarray
     macros: np.ndarray
-    blend: int                # 0: identity, 1: radial shell blending
+    blend: int                # 0: identity, 1: radial blending (shell, annulus)
     dt: float
     substeps: int
     steps: int
@@ -450,9 +508,28 @@ def shell3d(level: int = 5, subdiv: int = 4, layers: int = 4) -> Workload:
                     extra={"modes": sm, "h_min": h_min})
 
 
+ANNULUS_STEPS = 63  # tau = 2 pi / 63, about 0.1 (Sec. 4, Table 4)
+
+
+def annulus2d(level: int = 4, kappa: float = 1e-3) -> Workload:
+    """Advection-diffusion on the blended annulus r in [0.5, 1.5] (Sec. 4,
+    Table 4): 6 sectors x 2 layers of macro triangles (levels 4, 5, 6 give
+    the printed 12,480 / 49,536 / 197,376 P2 DoFs), u = (-x2, x1), the
+    moving Gaussian hill, one revolution in 63 steps of tau = 2 pi / 63, one
+    RK4 step per tau (b = 1: the field is interpolated every step)."""
+    v, m = annulus()
+    hill = MovingGaussian(kappa)
+    return Workload("annulus2d", 2, level, v, m, 1, 2.0 * math.pi / ANNULUS_STEPS, 1, ANNULUS_STEPS, True,
+                    circular_velocity, lambda x: hill(x, hill.t0),
+                    "annulus r in [0.5, 1.5], 6x2 macro triangles, radial blending; rotation (-x2, x1); "
+                    "Gaussian hill, kappa %g" % kappa,
+                    extra={"kappa": kappa, "hill": hill})
+
+
 CONFIGS = {
     "rotation2d": rotation2d,
     "swirl3d": swirl3d,
     "shell3d": shell3d,
     "plume3d": plume3d,
+    "annulus2d": annulus2d,
 }

@@ -38,11 +38,11 @@ def field_cpu(fn, xc, *args):
 class Pair:
     """A workload set up on both sides."""
 
-    def __init__(self, wl, level=None, precision=mmoc.MMOC_FP64, options=None):
+    def __init__(self, wl, level=None, precision=mmoc.MMOC_FP64, options=None, order=None):
         self.wl = wl
         self.level = wl.level if level is None else level
-        self.tr = mmoc.Tracer.from_workload(wl, precision=precision, level=self.level, options=options)
-        self.om = O.Mesh.from_workload(wl, level=self.level)
+        self.tr = mmoc.Tracer.from_workload(wl, precision=precision, level=self.level, options=options, order=order)
+        self.om = O.Mesh.from_workload(wl, level=self.level, order=order or 2)
         assert self.tr.N == self.om.N
         self.xg = self.tr.dof_coords()
         torch.cuda.synchronize()

@@ -205,3 +205,136 @@ def test_paper_table1_b_infinity(oracle_mod):
     dm = m.mass_quadform(one, ch) / m.mass_quadform(one, c0) - 1
     assert h0 < 10 * gold["H0"] and abs(dm) < 1e-12
     assert abs((ch.max() - ch.min()) - gold["var"]) < 1e-4
+
+
+# ---------------------------------------------------------------- general explicit RK (Sec. 3.1)
+
+from rk_tableaux import TABLEAUX, stability_matrix, tableau  # noqa: E402
+
+
+@pytest.mark.parametrize("name", list(TABLEAUX))
+def test_general_rk_linear_field_matches_stability_polynomial(oracle_mod, name):
+    """Any explicit RK method applied to u = Om (x - c), Om skew, advances
+    x - c by its stability matrix R(-h Om) per sub-step; P2 reproduces the
+    linear field exactly, so the traced departure points are that product."""
+    rng = np.random.default_rng(31)
+    wl, m, x = setup(oracle_mod, W.swirl3d, 2)
+    K = rng.normal(size=(3, 3))
+    Om = K - K.T
+    cen = np.full(3, 0.5)
+    U = Om @ (x - cen[:, None])
+    dt, S = 0.3, 3
+    h = dt / S
+    A, b, c, _ = tableau(name)
+    _, X, _ = m.trace(U, None, np.zeros(m.N), dt, S, tableau=(A, b, c))
+    ref = cen[:, None] + np.linalg.matrix_power(stability_matrix(name, -h * Om), S) @ (x - cen[:, None])
+    assert np.abs(X - ref).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", list(TABLEAUX))
+def test_general_rk_time_linear_translation(oracle_mod, name):
+    """u^n = a, u^{n+1} = b' everywhere: every stage sees the constant
+    (1 - theta) a + theta b' at its node theta = 1 - (j + c_i)/S, so
+    X = x - h sum_j sum_i b_i ((1 - theta_ij) a + theta_ij b')."""
+    rng = np.random.default_rng(32)
+    wl, m, x = setup(oracle_mod, W.rotation2d, 2)
+    a, bb = rng.normal(size=2) * 0.4, rng.normal(size=2) * 0.4
+    A, b, c, p = tableau(name)
+    dt, S = 0.2, 3
+    h = dt / S
+    _, X, _ = m.trace(np.tile(a[:, None], (1, m.N)), np.tile(bb[:, None], (1, m.N)), np.zeros(m.N), dt, S,
+                      tableau=(A, b, c))
+    disp = np.zeros(2)
+    for j in range(S):
+        for i in range(b.shape[0]):
+            th = 1.0 - (j + c[i]) / S
+            disp += h * b[i] * ((1 - th) * a + th * bb)
+    assert np.abs(X - (x - disp[:, None])).max() < 1e-14
+    if p >= 2:  # exact quadrature of a linear integrand
+        assert np.abs(X - (x - dt * 0.5 * (a + bb)[:, None])).max() < 1e-14
+
+
+def test_general_rk_rk4_tableau_equals_rk4(oracle_mod):
+    wl, m, x = setup(oracle_mod, W.swirl3d, 2)
+    xt = torch.from_numpy(x.T.copy())
+    U0 = W.swirl_velocity(xt, 0.3).numpy().T.copy()
+    U1 = W.swirl_velocity(xt, 0.3 + wl.dt).numpy().T.copy()
+    c0 = W.two_blobs(xt).numpy()
+    ch, X, _ = m.trace(U0, U1, c0, wl.dt, 4)
+    A, b, c, _ = tableau("rk4")
+    ch2, X2, _ = m.trace(U0, U1, c0, wl.dt, 4, tableau=(A, b, c))
+    assert np.abs(X - X2).max() < 1e-14 and np.abs(ch - ch2).max() < 1e-13
+
+
+@pytest.mark.parametrize("name", ["heun", "midpoint", "rk3", "rk38"])
+def test_general_rk_convergence_order(oracle_mod, name):
+    """The non-commuting time-dependent linear field of the RK4 test: the
+    error of each method falls by 2^p per halving of h."""
+    wl, m, x = setup(oracle_mod, W.swirl3d, 1)
+    A0 = np.array([[0.0, 1.0, 0.3], [-1.0, 0.0, 0.2], [-0.3, -0.2, 0.0]])
+    A1 = np.array([[0.1, 0.0, -0.8], [0.4, -0.3, 0.5], [0.8, -0.5, 0.2]])
+    dt = 0.8
+    U0, U1 = A0 @ x, A1 @ x
+    ids = np.arange(0, m.N, 5)
+
+    def exact(p0):
+        f = lambda t, y: (((1 - t / dt) * A0 + (t / dt) * A1) @ y)
+        return solve_ivp(f, (dt, 0.0), p0, rtol=1e-13, atol=1e-14, method="DOP853").y[:, -1]
+
+    ref = np.stack([exact(x[:, i]) for i in ids], axis=1)
+    A, b, c, p = tableau(name)
+    errs = []
+    for S in (8, 16, 32):
+        _, X, _ = m.trace(U0, U1, np.zeros(m.N), dt, S, ids=ids, tableau=(A, b, c))
+        errs.append(np.abs(X - ref).max())
+    rates = [np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])]
+    assert min(rates) > p - 0.3, (name, rates)
+
+
+# ---------------------------------------------------------------- traces across several steps (Sec. 2.3.3)
+
+
+def test_span_single_interval_is_the_step(oracle_mod):
+    wl, m, x = setup(oracle_mod, W.swirl3d, 2)
+    xt = torch.from_numpy(x.T.copy())
+    U0 = W.swirl_velocity(xt, 0.3).numpy().T.copy()
+    U1 = W.swirl_velocity(xt, 0.3 + wl.dt).numpy().T.copy()
+    c0 = W.two_blobs(xt).numpy()
+    ch, X, _ = m.trace(U0, U1, c0, wl.dt, 3)
+    ch2, X2, _ = m.trace_span([U0, U1], c0, wl.dt, 3)
+    assert np.array_equal(X, X2) and np.array_equal(ch, ch2)
+
+
+def test_span_piecewise_linear_translation(oracle_mod):
+    """Spatially constant levels a_l: RK4 integrates a velocity linear in time
+    exactly on each sub-step, and every sub-step lies in one interval, so
+    X = x - sum_l tau (a_l + a_{l+1}) / 2."""
+    rng = np.random.default_rng(41)
+    wl, m, x = setup(oracle_mod, W.swirl3d, 2)
+    a = rng.normal(size=(5, 3)) * 0.2
+    levels = [np.tile(al[:, None], (1, m.N)) for al in a]
+    tau = 0.07
+    for S in (1, 2):
+        _, X, _ = m.trace_span(levels, np.zeros(m.N), tau, S)
+        disp = sum(tau * 0.5 * (a[l] + a[l + 1]) for l in range(4))
+        assert np.abs(X - (x - disp[:, None])).max() < 1e-14
+
+
+def test_span_swirl_period_is_identity(oracle_mod):
+    """Levels of the swirl at t_k = k T / K, k = 0..K: the piecewise-linear
+    interpolation of g(t) = cos(pi t / T) at nodes symmetric about T/2 has
+    zero integral over [0, T], and the field is g(t) v(x), so the exact flow
+    map over the period is the identity.  RK4 approaches it as the sub-step
+    shrinks; the P2 velocity is only continuous across element faces, so
+    the observed rate is below four (the same bound as the single-step
+    period test: a factor above 30 per fourfold refinement)."""
+    wl, m, x = setup(oracle_mod, W.swirl3d, 2)
+    xt = torch.from_numpy(x.T.copy())
+    K = 6
+    tau = W.SWIRL_T / K
+    levels = [W.swirl_velocity(xt, k * tau).numpy().T.copy() for k in range(K + 1)]
+    e = []
+    for S in (4, 16):
+        _, X, _ = m.trace_span(levels, np.zeros(m.N), tau, S)
+        e.append(np.abs(X - x).max())
+    assert e[0] / e[1] > 30 and e[1] < 1e-5
