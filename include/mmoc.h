@@ -316,6 +316,78 @@ const char* mmoc_last_error(const mmoc_ctx* ctx);
 /* Frees the context and all library-owned device memory (synchronises). */
 void mmoc_destroy(mmoc_ctx* ctx);
 
+/* ----------------------------------------------------------------------
+ * Diffusion: the Theta-method step of Sec. 2.2 (eq. linear-system), the
+ * diffusion line of Alg. 1.  Alg. 2 (Strang splitting) is two calls with
+ * tau / 2 around the advection step.
+ *
+ * The Galerkin matrices M_ij = (phi_j, phi_i) and A_ij = (grad phi_j,
+ * grad phi_i) over the physical domain are assembled on the device at the
+ * first call that needs them (P2, or P1 for an order-1 context), in CSR form
+ * over the unique DoFs.  Integrals are taken through the element map
+ * Phi(affine micro simplex) with the collapsed Gauss rule of 4 points per
+ * direction on the reference simplex: exact for the unblended P2 matrices,
+ * and a quadrature of the smooth blended integrands otherwise.  The sums are
+ * taken in a fixed order, so the matrices are bitwise reproducible.  All
+ * vectors are float64 device arrays of N entries in the unique DoF order,
+ * whatever the context's precision.
+ * ---------------------------------------------------------------------- */
+typedef enum { MMOC_MAT_MASS = 0, MMOC_MAT_STIFFNESS = 1 } mmoc_matrix;
+
+/* Assembles M and A now (otherwise done by the first call below that needs
+ * them); *nnz (optional) receives the number of stored entries per matrix.
+ * Synchronises the stream.  Errors: MMOC_E_STATE before a mesh is uploaded,
+ * MMOC_E_UNSUPPORTED for meshes beyond 32-bit CSR indices. */
+mmoc_status mmoc_fe_assemble(mmoc_ctx* ctx, int64_t* nnz);
+
+/* Copies one matrix to host memory: row_ptr [N+1] (int64), cols [nnz]
+ * (ascending within each row) and vals [nnz]; each pointer may be NULL to
+ * skip it.  Synchronises the stream. */
+mmoc_status mmoc_fe_export(mmoc_ctx* ctx, mmoc_matrix which, int64_t* row_ptr, int32_t* cols, double* vals);
+
+/* y = M x or y = A x (device float64 [N]; x and y must not alias).
+ * Enqueued on the context's stream. */
+mmoc_status mmoc_fe_apply(mmoc_ctx* ctx, mmoc_matrix which, const double* x, double* y);
+
+/* Host uint8 [N]: 1 for DoFs on the domain boundary (lattice nodes of macro
+ * faces without a neighbour), 0 elsewhere.  This is the Dirichlet set of
+ * mmoc_diffusion_step (Sec. 2.2: V_h^D). */
+mmoc_status mmoc_boundary_mask(mmoc_ctx* ctx, uint8_t* mask);
+
+typedef struct {
+    double theta;             /* Theta in [0, 1]: 1 implicit Euler, 0.5 Crank-Nicolson */
+    double tau;               /* time step > 0 */
+    double kappa;             /* diffusivity >= 0 */
+    const double* q0;         /* device [N] load vector (q(t_n), phi_i), or NULL: zero */
+    const double* q1;         /* device [N] load vector (q(t_{n+1}), phi_i), or NULL: zero */
+    const double* dirichlet;  /* device [N]: values c_Gamma(t_{n+1}) at the boundary DoFs (other
+                                 entries are not read), or NULL: homogeneous Neumann everywhere */
+    double rtol;              /* CG stops at ||r||_2 <= rtol ||b||_2 (0: 1e-12) */
+    int max_iter;             /* CG iteration limit (0: 1000) */
+    int precond;              /* 0: plain CG, 1: Jacobi (diagonal) preconditioned CG */
+} mmoc_diffusion_args;
+
+typedef struct {
+    int iterations;       /* CG iterations taken */
+    int converged;        /* 1 when the tolerance was met (or the right-hand side is zero) */
+    double rel_residual;  /* ||r||_2 / ||b||_2 of the last iterate (recursive residual) */
+} mmoc_diffusion_info;
+
+/* One diffusion step (Sec. 2.2, eq. linear-system): solves
+ *   (M + tau Theta kappa A) c = (M - tau (1 - Theta) kappa A) c_hat
+ *                               + tau (Theta q1 + (1 - Theta) q0)
+ * for c_out by conjugate gradients (the matrix is symmetric positive
+ * definite), starting from c_hat.  With `dirichlet` given, the boundary DoFs
+ * take those values, their rows become identity rows and their known values
+ * move to the right-hand side of the other rows.  c_hat and c_out: device
+ * float64 [N], distinct.  The call synchronises the stream once per batch
+ * of iterations to read the convergence state; not converging within
+ * max_iter is reported in *info (optional), not as an error.
+ * Errors: MMOC_E_ARG for theta outside [0, 1], tau <= 0, kappa < 0,
+ * non-finite values or bad buffers; MMOC_E_STATE before a mesh. */
+mmoc_status mmoc_diffusion_step(mmoc_ctx* ctx, const mmoc_diffusion_args* args, const double* c_hat,
+                                double* c_out, mmoc_diffusion_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@
 #include "mmoc_internal.h"
 
 struct mlp_state;
+struct fe_state;
 
 struct mmoc_ctx {
     int dim = 0, level = 0, n = 0, m = 0;
@@ -45,7 +46,10 @@ struct mmoc_ctx {
     double* red_d = nullptr;  // partial sums of the metric reductions, red_cap doubles
     int64_t red_cap = 0;
 
+    std::vector<mmoc::MacroGeo> geo_h;  // host copy of the geometry table
+
     mlp_state* mlp = nullptr;
+    fe_state* fe = nullptr;
 };
 
 
@@ -63,6 +67,9 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
 // physical ring slot of logical velocity level l
 inline int phys_level(const mmoc_ctx* c, int l) { return (c->rot + l) % c->lev_cap; }
 void mmoc_mlp_free_state(mmoc_ctx* c);
+void mmoc_fe_free_state(mmoc_ctx* c);
+// lattice node (I, J, K), m >= I >= J >= K >= 0, in lexicographic order
+int64_t mmoc_lattice_index(int dim, int64_t I, int64_t J, int64_t K);
 
 #define HIPCHK(ctx, call, what)                                \
     do {                                                       \

@@ -171,6 +171,8 @@ void free_all(mmoc_ctx* c);
 
 }  // namespace
 
+int64_t mmoc_lattice_index(int dim, int64_t I, int64_t J, int64_t K) { return lattice_index(dim, I, J, K); }
+
 extern "C" {
 
 void mmoc_default_options(mmoc_options* o)
@@ -465,6 +467,7 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
     HIPCHK(c, hipMemcpyAsync(c->slot_uid_d, slot_uid.data(), sizeof(int32_t) * c->nslots, hipMemcpyHostToDevice, c->stream),
            "upload slot map");
     HIPCHK(c, hipStreamSynchronize(c->stream), "mesh upload");
+    c->geo_h = std::move(geo);
     c->mesh_ok = true;
     return MMOC_OK;
 }
@@ -739,6 +742,7 @@ namespace {
 void free_all(mmoc_ctx* c)
 {
     mmoc_mlp_free_state(c);
+    mmoc_fe_free_state(c);
     (void)hipFree(c->geo_d);
     (void)hipFree(c->owned_d);
     (void)hipFree(c->slot_uid_d);

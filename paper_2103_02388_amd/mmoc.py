@@ -23,6 +23,8 @@ MMOC_FP32_MIXED = 1
 MMOC_FP32_FIELDS = 2
 MMOC_BLEND_NONE = 0
 MMOC_BLEND_SHELL_RADIAL = 1
+MMOC_MAT_MASS = 0
+MMOC_MAT_STIFFNESS = 1
 
 STATUS = {0: "MMOC_OK", -1: "MMOC_E_ARG", -2: "MMOC_E_MESH", -3: "MMOC_E_STATE", -4: "MMOC_E_HIP",
           -5: "MMOC_E_NOMEM", -6: "MMOC_E_UNSUPPORTED"}
@@ -35,6 +37,7 @@ EXPORTED = [
     "mmoc_mlp_set_weights", "mmoc_mlp_infer", "mmoc_trace_step_surrogate", "mmoc_last_error",
     "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad", "mmoc_mass_inner", "mmoc_field_range",
     "mmoc_lookback_run", "mmoc_set_rk_tableau", "mmoc_cfl_time_step", "mmoc_set_level_count", "mmoc_trace_span",
+    "mmoc_fe_assemble", "mmoc_fe_export", "mmoc_fe_apply", "mmoc_boundary_mask", "mmoc_diffusion_step",
 ]
 
 
@@ -53,6 +56,19 @@ class mmoc_stats(C.Structure):
     _fields_ = [("n_particles", C.c_int64), ("n_outside", C.c_int64), ("n_multi_hop", C.c_int64),
                 ("n_bruteforce", C.c_int64), ("n_tieband", C.c_int64), ("n_nan", C.c_int64),
                 ("n_checked", C.c_int64), ("n_fallback", C.c_int64), ("max_check_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class mmoc_diffusion_args(C.Structure):
+    _fields_ = [("theta", C.c_double), ("tau", C.c_double), ("kappa", C.c_double), ("q0", C.c_void_p),
+                ("q1", C.c_void_p), ("dirichlet", C.c_void_p), ("rtol", C.c_double), ("max_iter", C.c_int),
+                ("precond", C.c_int)]
+
+
+class mmoc_diffusion_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("rel_residual", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -102,6 +118,11 @@ def lib():
         "mmoc_cfl_time_step": (st, [P, D, I, C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
         "mmoc_set_level_count": (st, [P, I]),
         "mmoc_trace_span": (st, [P, I, I, D, I, P, P]),
+        "mmoc_fe_assemble": (st, [P, C.POINTER(I64)]),
+        "mmoc_fe_export": (st, [P, I, P, P, P]),
+        "mmoc_fe_apply": (st, [P, I, P, P]),
+        "mmoc_boundary_mask": (st, [P, P]),
+        "mmoc_diffusion_step": (st, [P, C.POINTER(mmoc_diffusion_args), P, P, C.POINTER(mmoc_diffusion_info)]),
         "mmoc_last_error": (C.c_char_p, [P]),
         "mmoc_destroy": (None, [P]),
     }
@@ -298,6 +319,42 @@ def mmoc_trace_span(ctx, first, n_int, dt, substeps, c_hat: torch.Tensor, X: Opt
     _check(ctx, lib().mmoc_trace_span(ctx, int(first), int(n_int), float(dt), int(substeps), _ptr(c_hat), _ptr(X)))
 
 
+def mmoc_fe_assemble(ctx):
+    nnz = C.c_int64()
+    _check(ctx, lib().mmoc_fe_assemble(ctx, C.byref(nnz)))
+    return nnz.value
+
+
+def mmoc_fe_export(ctx, which, N):
+    """(row_ptr [N+1] int64, cols [nnz] int32, vals [nnz] float64) as numpy arrays."""
+    nnz = mmoc_fe_assemble(ctx)
+    rp = np.empty(N + 1, dtype=np.int64)
+    ci = np.empty(nnz, dtype=np.int32)
+    va = np.empty(nnz, dtype=np.float64)
+    vp = lambda x: x.ctypes.data_as(C.c_void_p)
+    _check(ctx, lib().mmoc_fe_export(ctx, int(which), vp(rp), vp(ci), vp(va)))
+    return rp, ci, va
+
+
+def mmoc_fe_apply(ctx, which, x: torch.Tensor, y: torch.Tensor):
+    _check(ctx, lib().mmoc_fe_apply(ctx, int(which), _ptr(x), _ptr(y)))
+
+
+def mmoc_boundary_mask(ctx, N):
+    out = np.empty(N, dtype=np.uint8)
+    _check(ctx, lib().mmoc_boundary_mask(ctx, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def mmoc_diffusion_step(ctx, c_hat: torch.Tensor, c_out: torch.Tensor, theta, tau, kappa, q0=None, q1=None,
+                        dirichlet=None, rtol=0.0, max_iter=0, precond=1):
+    a = mmoc_diffusion_args(float(theta), float(tau), float(kappa), _ptr(q0), _ptr(q1), _ptr(dirichlet),
+                            float(rtol), int(max_iter), int(precond))
+    info = mmoc_diffusion_info()
+    _check(ctx, lib().mmoc_diffusion_step(ctx, C.byref(a), _ptr(c_hat), _ptr(c_out), C.byref(info)))
+    return info.as_dict()
+
+
 def mmoc_last_error(ctx):
     return lib().mmoc_last_error(ctx).decode()
 
@@ -396,6 +453,33 @@ class Tracer:
 
     def field_range(self, c):
         return mmoc_field_range(self.ctx, c)
+
+    # ---------------------------------------------------- diffusion (Sec. 2.2)
+
+    def fe_assemble(self):
+        return mmoc_fe_assemble(self.ctx)
+
+    def fe_matrix(self, which):
+        """(row_ptr, cols, vals) of the mass (0) or stiffness (1) matrix, on the host."""
+        return mmoc_fe_export(self.ctx, which, self.N)
+
+    def fe_apply(self, which, x, y=None):
+        if y is None:
+            y = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        mmoc_fe_apply(self.ctx, which, x, y)
+        return y
+
+    def boundary_mask(self):
+        return mmoc_boundary_mask(self.ctx, self.N).astype(bool)
+
+    def diffusion_step(self, c_hat, tau, kappa, theta=1.0, q0=None, q1=None, dirichlet=None, rtol=1e-12,
+                       max_iter=0, precond=1, out=None):
+        """One Theta-method step; returns (c, info)."""
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        info = mmoc_diffusion_step(self.ctx, c_hat, out, theta, tau, kappa, q0, q1, dirichlet, rtol, max_iter,
+                                   precond)
+        return out, info
 
     def lookback_run(self, c0, tau, n_steps, b, substeps=1):
         """c^{n_steps} from c^0 with look-back distance b (b <= 0: infinity);
