@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--paths", default="fp64,fp32,fp32f", help="tracer paths to time (fp64 is the headline)")
+    ap.add_argument("--no-diffusion", action="store_true")
+    ap.add_argument("--diffusion-only", action="store_true",
+                    help="only the advection-diffusion sub-result (for profiling its kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (10 times), to scale HBM counters")
     args = ap.parse_args()
@@ -114,6 +117,9 @@ def main():
     from paper_2103_02388_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.diffusion_only:
+        print(json.dumps({"diffusion": time_diffusion()}), flush=True)
+        return
     wl = W.swirl3d()
     S = args.substeps
     results = {}
@@ -170,6 +176,8 @@ def main():
                               "note": "float32 field records, float64 arithmetic"}
     if not args.no_surrogate:
         out["surrogate"] = time_surrogate(wl, S, min(args.steps, 50), min(args.warmup, 5), results)
+    if not args.no_diffusion:
+        out["diffusion"] = time_diffusion()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, S)
     print(json.dumps(out), flush=True)
@@ -290,6 +298,110 @@ def time_surrogate(wl, S, steps, warmup, results):
     if "fp32" in results:
         out["speedup_vs_fp32_step"] = out["value"] / results["fp32"]["value"]
     return out
+
+
+def spmv_bytes(N, nnz):
+    """algorithmic HBM bytes of y = V x in CSR: values and column indices
+    once, row pointers, x read once, y written once"""
+    return nnz * (8 + 4) + (N + 1) * 4 + N * 8 + N * 8
+
+
+def time_diffusion():
+    """Advection-diffusion on the blended annulus (Sec. 4, Table 4's largest
+    mesh: level 6, 197,376 P2 DoFs, kappa = 1e-3, tau = 2 pi / 63, one RK4
+    step per tau).  One step = the trace of every DoF and the implicit-Euler
+    diffusion solve (Jacobi-preconditioned CG to 1e-12) with the exact
+    solution as Dirichlet data, as in Alg. 1; the Dirichlet data of all 63
+    steps are resident before timing.  The matrix assembly is timed on its
+    own.  The SpMV roofline entry is for the CSR operator apply on a larger
+    annulus (level 8, 3,148,800 DoFs) whose matrix does not fit in the
+    last-level cache."""
+    import math
+    import torch
+    from paper_2103_02388_amd import mmoc
+    from paper_2103_02388_amd import workloads as W
+
+    kappa = 1e-3
+    wl = W.annulus2d(level=6, kappa=kappa)
+    tr = mmoc.Tracer.from_workload(wl)
+    N = tr.N
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nnz = tr.fe_assemble()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    x = tr.dof_coords()
+    xt = x.t().contiguous()
+    hill = wl.extra["hill"]
+    tr.set_stationary(True)
+    tr.set_velocity(0, wl.velocity(xt).t().contiguous())
+    c0 = hill(xt, hill.t0).contiguous()
+    G = torch.stack([hill(xt, hill.t0 + (k + 1) * wl.dt) for k in range(wl.steps)]).contiguous()
+    ch = torch.empty_like(c0)
+
+    def run(timed):
+        c, nxt = c0.clone(), torch.empty_like(c0)
+        iters, tr_ms = 0, 0.0
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(wl.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(wl.steps):
+            tr.set_scalar(c)
+            ev[k][0].record()
+            tr.trace_step(wl.dt, wl.substeps, c_hat=ch, want_X=False)
+            ev[k][1].record()
+            nxt, info = tr.diffusion_step(ch, wl.dt, kappa, 1.0, dirichlet=G[k], out=nxt)
+            iters += info["iterations"]
+            c, nxt = nxt, c
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        tr_ms = sum(a.elapsed_time(b) for a, b in ev)
+        return c, wall, tr_ms, iters
+
+    run(False)
+    c, wall, tr_ms, iters = run(True)
+    ex = G[-1]
+    e = (ex - c).contiguous()
+    h0 = math.sqrt(float((e * tr.fe_apply(mmoc.MMOC_MAT_MASS, e)).sum()))
+    ep = float(c.max() / ex.max() - 1.0)
+    steps = wl.steps
+    diff_ms = wall - tr_ms
+    # the operator apply on its own: Table 4 mesh (cache resident) and a large mesh
+    def spmv_time(t, reps=50):
+        v = torch.ones(t.N, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(v)
+        for _ in range(3):
+            t.fe_apply(mmoc.MMOC_MAT_MASS, v, y)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            t.fe_apply(mmoc.MMOC_MAT_MASS, v, y)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+    small_ms = spmv_time(tr)
+    tr.close()
+    big = mmoc.Tracer.from_workload(W.annulus2d(level=8, kappa=kappa))
+    bnnz = big.fe_assemble()
+    big_ms = spmv_time(big)
+    bN = big.N
+    big.close()
+    achieved = spmv_bytes(bN, bnnz) / (big_ms * 1e-3)
+    return {
+        "workload": "annulus2d: r in [0.5, 1.5], 6x2 macro triangles, radial blending, level 6, 197376 P2 DoFs; "
+                    "rotation (-x2, x1); Gaussian hill kappa 1e-3; tau = 2 pi/63, one RK4 step per tau, 63 steps; "
+                    "implicit Euler, Jacobi CG to 1e-12, Dirichlet data from the exact solution",
+        "dofs": N, "nnz": nnz, "steps": steps,
+        "value": N / (wall / steps * 1e-3), "unit": "DoFs advanced/s (trace + diffusion solve)",
+        "ms_per_step": wall / steps, "trace_ms_per_step": tr_ms / steps, "diffusion_ms_per_step": diff_ms / steps,
+        "cg_iterations_per_step": iters / steps, "us_per_cg_iteration": diff_ms * 1e3 / max(iters, 1),
+        "assembly_ms": setup_ms, "H0_error": h0, "E_peak": ep, "paper_H0": 4.32e-3, "paper_E_peak": 3.98e-3,
+        "spmv_table4_mesh_us": small_ms * 1e3,
+        "roofline": {"bound": "hbm", "kernel": "spmv_kernel (CSR, mass matrix)", "mesh": "annulus2d level 8",
+                     "dofs": bN, "nnz": bnnz, "kernel_ms": big_ms, "bytes_per_launch": spmv_bytes(bN, bnnz),
+                     "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": achieved / PEAK_HBM,
+                     "traffic": None},
+    }
 
 
 def cpu_baseline(wl, S):

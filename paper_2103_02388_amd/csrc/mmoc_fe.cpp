@@ -25,18 +25,21 @@ struct fe_state {
     int64_t nel = 0, nnz = 0;
     int32_t* rp_d = nullptr;  // [N + 1]
     int32_t* ci_d = nullptr;  // [nnz], ascending within a row
+    int4* rb_d = nullptr;     // [nrb] row blocks: first row, end row, first entry, end entry
+    int64_t nrb = 0;
     double* mv_d = nullptr;   // mass matrix values
     double* av_d = nullptr;   // stiffness matrix values
     double* ev_d = nullptr;   // system matrix of the last solve
     double* dinv_d = nullptr;
     uint8_t* dir_d = nullptr;  // boundary DoFs
     std::vector<uint8_t> bmask;
-    double *b_d = nullptr, *r_d = nullptr, *p_d = nullptr, *q_d = nullptr, *part_d = nullptr;
+    double *b_d = nullptr, *r_d = nullptr, *u_d = nullptr, *w_d = nullptr, *p_d = nullptr, *s_d = nullptr;
+    double* part_d = nullptr;
     fe::CgScalars* sc_d = nullptr;
-    unsigned* ticket_d = nullptr;
     // what ev_d / dinv_d hold: s1, Dirichlet rows on/off, preconditioner
     double e_s1 = NAN;
     int e_dir = -1, e_pre = -1;
+    int last_iters = 0;  // iterations of the last converged solve: the next one enqueues as many at once
 };
 
 namespace {
@@ -180,25 +183,36 @@ mmoc_status ensure_fe(mmoc_ctx* c)
             }
         }
 
-    // --- CSR pattern: the (row, column) pairs of all elements, sorted
-    std::vector<uint64_t> keys;
-    keys.reserve((size_t)nel * nb * nb);
-    for (int64_t e = 0; e < nel; ++e)
-        for (int i = 0; i < nb; ++i)
-            for (int j = 0; j < nb; ++j)
-                keys.push_back((uint64_t)(uint32_t)dof[e * nb + i] << 32 | (uint32_t)dof[e * nb + j]);
-    std::sort(keys.begin(), keys.end());
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-    const int64_t nnz = (int64_t)keys.size();
-    if (nnz >= (int64_t)INT32_MAX) return fail(c, MMOC_E_UNSUPPORTED, "matrix too large for 32-bit indices");
-    std::vector<int32_t> rp((size_t)N + 1, 0), ci((size_t)nnz);
-    for (int64_t k = 0; k < nnz; ++k) {
-        rp[(keys[k] >> 32) + 1] += 1;
-        ci[k] = (int32_t)(keys[k] & 0xffffffffu);
+    // --- CSR pattern: per row, the columns of every element that holds the
+    // row's DoF (bucketed by row, then sorted and deduplicated row by row)
+    std::vector<int64_t> off((size_t)N + 1, 0);
+    for (int64_t t = 0; t < nel * nb; ++t) off[(size_t)dof[t] + 1] += nb;
+    for (int64_t i = 0; i < N; ++i) off[i + 1] += off[i];
+    std::vector<int32_t> all((size_t)off[N]);
+    {
+        std::vector<int64_t> fill(off.begin(), off.end() - 1);
+        for (int64_t e = 0; e < nel; ++e)
+            for (int i = 0; i < nb; ++i) {
+                const int32_t r = dof[e * nb + i];
+                for (int j = 0; j < nb; ++j) all[fill[r]++] = dof[e * nb + j];
+            }
     }
-    for (int64_t i = 0; i < N; ++i) rp[i + 1] += rp[i];
-    keys.clear();
-    keys.shrink_to_fit();
+    std::vector<int32_t> rp((size_t)N + 1, 0);
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t* b = all.data() + off[i];
+        int32_t* en = all.data() + off[i + 1];
+        std::sort(b, en);
+        en = std::unique(b, en);
+        std::memmove(all.data() + nnz, b, sizeof(int32_t) * (size_t)(en - b));  // compact: nnz <= off[i]
+        nnz += en - b;
+        rp[i + 1] = (int32_t)std::min<int64_t>(nnz, INT32_MAX);
+    }
+    if (nnz >= (int64_t)INT32_MAX) return fail(c, MMOC_E_UNSUPPORTED, "matrix too large for 32-bit indices");
+    all.resize((size_t)nnz);
+    std::vector<int32_t> ci = std::move(all);
+    off.clear();
+    off.shrink_to_fit();
 
     // --- per slot, the element entries that sum into it, in element order
     std::vector<int32_t> slot_of((size_t)nel * nb * nb);
@@ -222,6 +236,19 @@ mmoc_status ensure_fe(mmoc_ctx* c)
     }
     slot_of.clear();
     slot_of.shrink_to_fit();
+
+    // --- row blocks: consecutive rows, at most kRowsPerBlock of them and
+    // at most kLds entries in all
+    std::vector<int32_t> rb(1, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t len = rp[i + 1] - rp[i];
+        if (len > fe::kLds) return fail(c, MMOC_E_UNSUPPORTED, "matrix row %lld has too many entries", (long long)i);
+        const int32_t r0 = rb.back();
+        if (i - r0 == fe::kRowsPerBlock || rp[i + 1] - rp[r0] > fe::kLds) rb.push_back((int32_t)i);
+    }
+    rb.push_back((int32_t)N);
+    std::vector<int4> rbh(rb.size() - 1);
+    for (size_t b = 0; b + 1 < rb.size(); ++b) rbh[b] = make_int4(rb[b], rb[b + 1], rp[rb[b]], rp[rb[b + 1]]);
 
     // --- boundary DoFs: lattice nodes on macro faces without a neighbour
     std::vector<uint8_t> bmask((size_t)N, 0);
@@ -269,6 +296,8 @@ mmoc_status ensure_fe(mmoc_ctx* c)
     const size_t ne = (size_t)nel * nb * nb;
     if ((st = fe_alloc(c, &F->rp_d, (size_t)N + 1, "CSR rows")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &F->ci_d, (size_t)nnz, "CSR columns")) != MMOC_OK) return bail(st);
+    if ((st = fe_alloc(c, &F->rb_d, rbh.size(), "CSR row blocks")) != MMOC_OK) return bail(st);
+    F->nrb = (int64_t)rbh.size();  // >= 1: a mesh has DoFs
     if ((st = fe_alloc(c, &F->mv_d, (size_t)nnz, "mass matrix")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &F->av_d, (size_t)nnz, "stiffness matrix")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &F->ev_d, (size_t)nnz, "system matrix")) != MMOC_OK) return bail(st);
@@ -276,11 +305,13 @@ mmoc_status ensure_fe(mmoc_ctx* c)
     if ((st = fe_alloc(c, &F->dir_d, (size_t)N, "boundary mask")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &F->b_d, (size_t)N, "CG vector b")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &F->r_d, (size_t)N, "CG vector r")) != MMOC_OK) return bail(st);
+    if ((st = fe_alloc(c, &F->u_d, (size_t)N, "CG vector u")) != MMOC_OK) return bail(st);
+    if ((st = fe_alloc(c, &F->w_d, (size_t)N, "CG vector w")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &F->p_d, (size_t)N, "CG vector p")) != MMOC_OK) return bail(st);
-    if ((st = fe_alloc(c, &F->q_d, (size_t)N, "CG vector q")) != MMOC_OK) return bail(st);
-    if ((st = fe_alloc(c, &F->part_d, (size_t)4 * fe::kRedBlocks, "CG partial sums")) != MMOC_OK) return bail(st);
+    if ((st = fe_alloc(c, &F->s_d, (size_t)N, "CG vector s")) != MMOC_OK) return bail(st);
+    if ((st = fe_alloc(c, &F->part_d, (size_t)fe::P_SLOTS * fe::kMaxRedBlocks, "CG partial sums")) != MMOC_OK)
+        return bail(st);
     if ((st = fe_alloc(c, &F->sc_d, 1, "CG scalars")) != MMOC_OK) return bail(st);
-    if ((st = fe_alloc(c, &F->ticket_d, 1, "CG ticket")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &el_d, (size_t)nel, "element table")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &rule_d, 1, "quadrature rule")) != MMOC_OK) return bail(st);
     if ((st = fe_alloc(c, &me_d, ne, "element mass matrices")) != MMOC_OK) return bail(st);
@@ -294,12 +325,12 @@ mmoc_status ensure_fe(mmoc_ctx* c)
     };
     up(F->rp_d, rp.data(), sizeof(int32_t) * rp.size());
     up(F->ci_d, ci.data(), sizeof(int32_t) * ci.size());
+    up(F->rb_d, rbh.data(), sizeof(int4) * rbh.size());
     up(F->dir_d, F->bmask.data(), F->bmask.size());
     up(el_d, el.data(), sizeof(fe::Elem) * el.size());
     up(rule_d, &rule, sizeof rule);
     up(cptr_d, cptr.data(), sizeof(int64_t) * cptr.size());
     up(contrib_d, contrib.data(), sizeof(int32_t) * contrib.size());
-    if (e == hipSuccess) e = hipMemsetAsync(F->ticket_d, 0, sizeof(unsigned), c->stream);
     if (e == hipSuccess)
         e = fe::launch_element_matrices(d, order, c->blend, c->geo_d, el_d, nel, c->n, rule_d, me_d, ae_d, c->stream);
     if (e == hipSuccess) e = fe::launch_gather(nnz, cptr_d, contrib_d, me_d, ae_d, F->mv_d, F->av_d, c->stream);
@@ -312,15 +343,21 @@ mmoc_status ensure_fe(mmoc_ctx* c)
     return MMOC_OK;
 }
 
+fe::Csr csr_of(const mmoc_ctx* c)
+{
+    const fe_state* F = c->fe;
+    return fe::Csr{c->N, F->nrb, F->rp_d, F->ci_d, F->rb_d};
+}
+
 }  // namespace
 
 void mmoc_fe_free_state(mmoc_ctx* c)
 {
     fe_state* F = c->fe;
     if (!F) return;
-    for (void* p : {(void*)F->rp_d, (void*)F->ci_d, (void*)F->mv_d, (void*)F->av_d, (void*)F->ev_d, (void*)F->dinv_d,
-                    (void*)F->dir_d, (void*)F->b_d, (void*)F->r_d, (void*)F->p_d, (void*)F->q_d, (void*)F->part_d,
-                    (void*)F->sc_d, (void*)F->ticket_d})
+    for (void* p : {(void*)F->rp_d, (void*)F->ci_d, (void*)F->rb_d, (void*)F->mv_d, (void*)F->av_d, (void*)F->ev_d,
+                    (void*)F->dinv_d, (void*)F->dir_d, (void*)F->b_d, (void*)F->r_d, (void*)F->u_d, (void*)F->w_d,
+                    (void*)F->p_d, (void*)F->s_d, (void*)F->part_d, (void*)F->sc_d})
         (void)hipFree(p);
     delete F;
     c->fe = nullptr;
@@ -371,7 +408,7 @@ mmoc_status mmoc_fe_apply(mmoc_ctx* c, mmoc_matrix which, const double* x, doubl
     if ((st = check_dev(c, y, bytes, 8, "y")) != MMOC_OK) return st;
     if (x == y) return fail(c, MMOC_E_ARG, "x and y must not alias");
     fe_state* F = c->fe;
-    HIPCHK(c, fe::launch_spmv(c->N, F->rp_d, F->ci_d, which == MMOC_MAT_MASS ? F->mv_d : F->av_d, x, y, c->stream),
+    HIPCHK(c, fe::launch_spmv(csr_of(c), which == MMOC_MAT_MASS ? F->mv_d : F->av_d, x, y, c->stream),
            "operator apply");
     return MMOC_OK;
 }
@@ -421,23 +458,30 @@ mmoc_status mmoc_diffusion_step(mmoc_ctx* c, const mmoc_diffusion_args* args, co
         F->e_dir = dir;
         F->e_pre = A.precond;
     }
-    fe::RhsArgs ra{c->N, F->rp_d, F->ci_d, F->mv_d, F->av_d, s1, s2, A.tau * (1.0 - A.theta), A.tau * A.theta,
+    fe::RhsArgs ra{csr_of(c), F->mv_d, F->av_d, s1, s2, A.tau * (1.0 - A.theta), A.tau * A.theta,
                    c_hat, A.q0, A.q1, A.dirichlet, is_dir, F->b_d, c_out};
     HIPCHK(c, fe::launch_rhs(ra, c->stream), "right-hand side");
-    fe::CgArgs ca{c->N, F->rp_d, F->ci_d, F->ev_d, F->dinv_d, F->b_d, c_out, F->r_d, F->p_d, F->q_d,
-                  F->part_d, F->ticket_d, F->sc_d, rtol * rtol, max_iter};
+    fe::CgArgs ca{csr_of(c), F->ev_d, F->dinv_d, F->b_d, c_out, F->r_d, F->u_d, F->w_d, F->p_d, F->s_d,
+                  F->part_d, F->sc_d, rtol * rtol};
     HIPCHK(c, fe::launch_cg_init(ca, c->stream), "CG start");
+    // Iterations are enqueued in batches and the state is read back after
+    // each; iterations past the stop return at once.  Successive solves of
+    // a time loop take similar counts, so the first batch is the last
+    // solve's count plus the iteration that detects the stop, then small
+    // batches follow.
     fe::CgScalars h{};
     int launched = 0;
+    int next = F->last_iters > 0 ? F->last_iters + 1 : 16;
     for (;;) {
         HIPCHK(c, hipMemcpyAsync(&h, F->sc_d, sizeof h, hipMemcpyDeviceToHost, c->stream), "CG state");
         HIPCHK(c, hipStreamSynchronize(c->stream), "CG state");
         if (h.done || launched >= max_iter) break;
-        // iterations are enqueued in batches; those after convergence return at once
-        const int batch = std::min(max_iter - launched, launched < 16 ? 16 : 32);
-        for (int k = 0; k < batch; ++k) HIPCHK(c, fe::launch_cg_iteration(ca, c->stream), "CG iteration");
+        const int batch = std::min(max_iter - launched, next);
+        for (int k = 0; k < batch; ++k) HIPCHK(c, fe::launch_cg_iteration(ca, launched + k, c->stream), "CG iteration");
         launched += batch;
+        next = F->last_iters > 0 ? 4 : 32;
     }
+    if (h.done == 1) F->last_iters = h.iters;
     if (info) {
         info->iterations = h.iters;
         info->converged = (h.done == 1 || h.done == 3) ? 1 : 0;

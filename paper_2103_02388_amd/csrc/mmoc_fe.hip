@@ -8,11 +8,16 @@
 // the element entries of every CSR slot in a fixed order (no atomics, so the
 // matrices are bitwise reproducible).
 //
-// Solve: conjugate gradients on the CSR matrix, float64.  The dot products
-// reduce through per-block partials that the last block to finish sums in a
-// fixed order (a ticket counter); the step scalars stay on the device, and
-// each kernel returns at once when the solve has converged, so that the host
-// can enqueue batches of iterations and read the state back once per batch.
+// Operators: a block takes a row block of the CSR matrix, stages the
+// products of its entries in LDS with consecutive threads (coalesced reads
+// of values and column indices), then each thread sums one row.
+//
+// Solve: conjugate gradients on the CSR matrix, float64.  Each reducing
+// kernel writes one partial sum per block; the next kernel's blocks all sum
+// those partials in the same fixed order, so every block derives the same
+// step scalars and stop decision without atomics.  Each kernel returns at
+// once when the solve has stopped, so that the host can enqueue batches of
+// iterations and read the state back once per batch.
 #include "mmoc_fe_internal.h"
 
 #include <math.h>
@@ -31,20 +36,13 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// coherent (L2) read of a value another block wrote in this launch
-__device__ __forceinline__ double load_l2(const double* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sums NV values over the block, publishes the block's sums as partials and
-// takes a ticket.  Returns true in the last block to finish, whose thread 0
-// then holds in tot[] the totals over all blocks, summed in block order.
+// Sum of v over the block, returned to every thread; fixed order (wave
+// butterflies, then the waves in order), so every block that sums the same
+// values gets the same bits.
 template <int NV>
-__device__ bool reduce_last(double (&v)[NV], double* part, unsigned* ticket, double (&tot)[NV])
+__device__ __forceinline__ void block_sum(double (&v)[NV])
 {
     __shared__ double sh[NV][kWaves];
-    __shared__ bool last;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -52,44 +50,57 @@ __device__ bool reduce_last(double (&v)[NV], double* part, unsigned* ticket, dou
         if (lane == 0) sh[k][wave] = w;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = sh[k][0];
-#pragma unroll
-            for (int q = 1; q < kWaves; ++q) s += sh[k][q];
-            part[k * kRedBlocks + blockIdx.x] = s;
-        }
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        acc[k] = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += kB) acc[k] += load_l2(part + k * kRedBlocks + b);
-    }
-    __syncthreads();  // sh is reused
+        double t = sh[k][0];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const double w = wave_sum(acc[k]);
-        if (lane == 0) sh[k][wave] = w;
+        for (int q = 1; q < kWaves; ++q) t += sh[k][q];
+        v[k] = t;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+}
+
+// totals of partial-sum slots written by the previous kernel (G blocks)
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, const int (&slot)[NV], int G,
+                                             double (&out)[NV])
+{
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = sh[k][0];
+    for (int k = 0; k < NV; ++k) out[k] = 0.0;
+    for (int b = threadIdx.x; b < G; b += kB)
 #pragma unroll
-            for (int q = 1; q < kWaves; ++q) s += sh[k][q];
-            tot[k] = s;
-        }
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < NV; ++k) out[k] += part[slot[k] * kMaxRedBlocks + b];
+    block_sum<NV>(out);
+}
+
+// Row block blk of a CSR matrix: f(k) for each of its entries is staged in
+// LDS by consecutive threads (coalesced reads of the values and column
+// indices), then thread t returns the sum over row r0 + t in entry order
+// (row = -1 for threads past the block's rows).
+template <typename F>
+__device__ __forceinline__ double stream_row_sum(const Csr& A, int4 h, double* __restrict__ buf, F f, int& row)
+{
+    const int r0 = h.x, r1 = h.y, base = h.z, end = h.w;
+    int k = base + (int)threadIdx.x;
+    // four independent entries in flight per thread
+    for (; k + 3 * kB < end; k += 4 * kB) {
+        const double a0 = f(k), a1 = f(k + kB), a2 = f(k + 2 * kB), a3 = f(k + 3 * kB);
+        buf[k - base] = a0;
+        buf[k + kB - base] = a1;
+        buf[k + 2 * kB - base] = a2;
+        buf[k + 3 * kB - base] = a3;
     }
-    return true;
+    for (; k < end; k += kB) buf[k - base] = f(k);
+    __syncthreads();
+    double s = 0.0;
+    row = -1;
+    if ((int)threadIdx.x < r1 - r0) {
+        row = r0 + (int)threadIdx.x;
+        const int e = A.rp[row + 1];
+        for (int k = A.rp[row]; k < e; ++k) s += buf[k - base];
+    }
+    __syncthreads();
+    return s;
 }
 
 // ------------------------------------------------------------- assembly
@@ -338,133 +349,214 @@ __global__ __launch_bounds__(kB) void build_e_kernel(int64_t N, const int32_t* _
     dinv[i] = precond ? 1.0 / diag : 1.0;
 }
 
-__global__ __launch_bounds__(kB) void spmv_kernel(int64_t N, const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ ci, const double* __restrict__ v,
-                                                  const double* __restrict__ x, double* __restrict__ y)
+__global__ __launch_bounds__(kB) void spmv_kernel(Csr A, const double* __restrict__ v, const double* __restrict__ x,
+                                                  double* __restrict__ y)
 {
-    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= N) return;
-    double acc = 0.0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc = fma(v[k], x[ci[k]], acc);
-    y[i] = acc;
+    __shared__ double buf[kLds];
+    for (int64_t blk = blockIdx.x; blk < A.nrb; blk += gridDim.x) {
+        int row;
+        const double s = stream_row_sum(A, A.rb[blk], buf, [&](int k) { return v[k] * x[A.ci[k]]; }, row);
+        if (row >= 0) y[row] = s;
+    }
 }
 
 __global__ __launch_bounds__(kB) void rhs_kernel(RhsArgs a)
 {
-    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= a.N) return;
-    if (a.is_dir && a.is_dir[i]) {
-        a.b[i] = a.g[i];
-        a.x[i] = a.g[i];
-        return;
+    __shared__ double buf[kLds];
+    for (int64_t blk = blockIdx.x; blk < a.A.nrb; blk += gridDim.x) {
+        int row;
+        const double s = stream_row_sum(
+            a.A, a.A.rb[blk], buf,
+            [&](int k) {
+                const int32_t j = a.A.ci[k];
+                const double m = a.mv[k], st = a.av[k];
+                double t = fma(-a.s2, st, m) * a.chat[j];
+                if (a.is_dir && a.is_dir[j]) t = fma(-fma(a.s1, st, m), a.g[j], t);
+                return t;
+            },
+            row);
+        if (row < 0) continue;
+        if (a.is_dir && a.is_dir[row]) {
+            a.b[row] = a.g[row];
+            a.x[row] = a.g[row];
+            continue;
+        }
+        double acc = s;
+        if (a.q0) acc = fma(a.w0, a.q0[row], acc);
+        if (a.q1) acc = fma(a.w1, a.q1[row], acc);
+        a.b[row] = acc;
+        a.x[row] = a.chat[row];
     }
-    double acc = 0.0;
-    for (int32_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
-        const int32_t j = a.ci[k];
-        const double m = a.mv[k], s = a.av[k];
-        acc = fma(fma(-a.s2, s, m), a.chat[j], acc);
-        if (a.is_dir && a.is_dir[j]) acc = fma(-fma(a.s1, s, m), a.g[j], acc);
-    }
-    if (a.q0) acc = fma(a.w0, a.q0[i], acc);
-    if (a.q1) acc = fma(a.w1, a.q1[i], acc);
-    a.b[i] = acc;
-    a.x[i] = a.chat[i];
 }
 
 // ------------------------------------------------------------------- CG
+//
+// Preconditioned CG in the Chronopoulos-Gear arrangement: the two inner
+// products of an iteration, gamma = (r, u) and delta = (E u, u) with
+// u = D^-1 r, come out of the same pass as the matrix product w = E u, so an
+// iteration is two kernels with one reduction point:
+//   beta = gamma_k / gamma_{k-1},  alpha = gamma_k / (delta_k - beta gamma_k / alpha_{k-1})
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,  u = D^-1 r
+// (p = u, s = w, alpha = gamma / delta at k = 0).  In exact arithmetic this
+// is the same iteration as the textbook CG; s stays equal to E p.
 
-__device__ __forceinline__ double row_dot(const CgArgs& a, int64_t i, const double* x)
-{
-    double acc = 0.0;
-    for (int32_t k = a.rp[i]; k < a.rp[i + 1]; ++k) acc = fma(a.ev[k], x[a.ci[k]], acc);
-    return acc;
-}
-
+// r = b - E x, u = D^-1 r; partials of r.r and b.b
 __global__ __launch_bounds__(kB) void cg_init_kernel(CgArgs a)
 {
-    double v[3] = {0.0, 0.0, 0.0};  // r.z, r.r, b.b
-    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.N; i += (int64_t)gridDim.x * kB) {
-        const double bi = a.b[i];
-        const double r = bi - row_dot(a, i, a.x);
-        const double z = a.dinv[i] * r;
-        a.r[i] = r;
-        a.p[i] = z;
-        v[0] = fma(r, z, v[0]);
-        v[1] = fma(r, r, v[1]);
-        v[2] = fma(bi, bi, v[2]);
-    }
-    double tot[3];
-    if (reduce_last<3>(v, a.part, a.ticket, tot) && threadIdx.x == 0) {
-        CgScalars* s = a.sc;
-        s->rz = tot[0];
-        s->rr = tot[1];
-        s->bb = tot[2];
-        s->thresh = a.rtol2 * (tot[2] > 0.0 ? tot[2] : tot[1]);
-        s->iters = 0;
-        s->alpha = s->beta = s->pq = 0.0;
-        s->done = tot[1] <= s->thresh ? (tot[2] > 0.0 ? 1 : 3) : 0;
-    }
-}
-
-// q = E p, p.q; alpha = r.z / p.q
-__global__ __launch_bounds__(kB) void cg_spmv_kernel(CgArgs a)
-{
-    if (a.sc->done) return;
-    double v[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.N; i += (int64_t)gridDim.x * kB) {
-        const double q = row_dot(a, i, a.p);
-        a.q[i] = q;
-        v[0] = fma(a.p[i], q, v[0]);
-    }
-    double tot[1];
-    if (reduce_last<1>(v, a.part, a.ticket, tot) && threadIdx.x == 0) {
-        CgScalars* s = a.sc;
-        s->pq = tot[0];
-        if (!(tot[0] > 0.0)) s->done = 2;
-        else s->alpha = s->rz / tot[0];
-    }
-}
-
-// x += alpha p, r -= alpha q, r.z and r.r; beta = r.z_new / r.z
-__global__ __launch_bounds__(kB) void cg_update_kernel(CgArgs a)
-{
-    if (a.sc->done) return;
-    const double alpha = a.sc->alpha;
+    __shared__ double buf[kLds];
     double v[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.N; i += (int64_t)gridDim.x * kB) {
-        a.x[i] = fma(alpha, a.p[i], a.x[i]);
-        const double r = fma(-alpha, a.q[i], a.r[i]);
+    for (int64_t blk = blockIdx.x; blk < a.A.nrb; blk += gridDim.x) {
+        int i;
+        const double ex = stream_row_sum(a.A, a.A.rb[blk], buf, [&](int k) { return a.ev[k] * a.x[a.A.ci[k]]; }, i);
+        if (i < 0) continue;
+        const double bi = a.b[i];
+        const double r = bi - ex;
         a.r[i] = r;
-        v[0] = fma(r, a.dinv[i] * r, v[0]);
-        v[1] = fma(r, r, v[1]);
+        a.u[i] = a.dinv[i] * r;
+        v[0] = fma(r, r, v[0]);
+        v[1] = fma(bi, bi, v[1]);
     }
-    double tot[2];
-    if (reduce_last<2>(v, a.part, a.ticket, tot) && threadIdx.x == 0) {
-        CgScalars* s = a.sc;
-        s->beta = tot[0] / s->rz;
-        s->rz = tot[0];
-        s->rr = tot[1];
-        s->iters += 1;
-        if (tot[1] <= s->thresh) s->done = 1;
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+        a.part[P_RR * kMaxRedBlocks + blockIdx.x] = v[0];
+        a.part[P_BB * kMaxRedBlocks + blockIdx.x] = v[1];
     }
 }
 
-// p = D^-1 r + beta p
-__global__ __launch_bounds__(kB) void cg_direction_kernel(CgArgs a)
+__global__ __launch_bounds__(kB) void cg_start_kernel(CgArgs a, int G)
 {
-    if (a.sc->done) return;
-    const double beta = a.sc->beta;
-    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= a.N) return;
-    a.p[i] = fma(beta, a.p[i], a.dinv[i] * a.r[i]);
+    const int slot[2] = {P_RR, P_BB};
+    double t[2];
+    sum_partials<2>(a.part, slot, G, t);
+    if (threadIdx.x == 0) {
+        CgScalars* s = a.sc;
+        s->rr = t[0];
+        s->bb = t[1];
+        s->thresh = a.rtol2 * (t[1] > 0.0 ? t[1] : t[0]);
+        s->iters = 0;
+        s->alpha[0] = s->alpha[1] = 0.0;
+        s->done = t[0] <= s->thresh ? (t[1] > 0.0 ? 1 : 3) : 0;
+    }
+}
+
+// w = E u; partials of gamma = r.u (slot by parity), delta = w.u and r.r
+__global__ __launch_bounds__(kB) void cg_spmv_kernel(CgArgs a, int par)
+{
+    // the stop flag and the first row block's header load together
+    const int done = a.sc->done;
+    int4 h = a.A.rb[blockIdx.x];  // the grid never exceeds the row blocks
+    if (done) return;
+    __shared__ double buf[kLds];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t blk = blockIdx.x; blk < a.A.nrb; blk += gridDim.x) {
+        if (blk != blockIdx.x) h = a.A.rb[blk];
+        int i;
+        const double w = stream_row_sum(a.A, h, buf, [&](int k) { return a.ev[k] * a.u[a.A.ci[k]]; }, i);
+        if (i < 0) continue;
+        a.w[i] = w;
+        const double r = a.r[i], u = a.u[i];
+        v[0] = fma(r, u, v[0]);
+        v[1] = fma(w, u, v[1]);
+        v[2] = fma(r, r, v[2]);
+    }
+    block_sum<3>(v);
+    if (threadIdx.x == 0) {
+        a.part[(P_G0 + par) * kMaxRedBlocks + blockIdx.x] = v[0];
+        a.part[P_DE * kMaxRedBlocks + blockIdx.x] = v[1];
+        a.part[P_RR * kMaxRedBlocks + blockIdx.x] = v[2];
+    }
+}
+
+struct RowVals {
+    double u, w, p, s, x, r, dinv;
+};
+
+__device__ __forceinline__ void load_row(const CgArgs& a, int i, RowVals& v)
+{
+    v.u = a.u[i];
+    v.w = a.w[i];
+    v.p = a.p[i];
+    v.s = a.s[i];
+    v.x = a.x[i];
+    v.r = a.r[i];
+    v.dinv = a.dinv[i];
+}
+
+// p = u + beta p, s = w + beta s (p = u, s = w at k = 0), x += alpha p,
+// r -= alpha s, u = D^-1 r
+__device__ __forceinline__ void update_row(const CgArgs& a, int i, const RowVals& v, int k, double alpha,
+                                           double beta)
+{
+    const double p = k == 0 ? v.u : fma(beta, v.p, v.u);
+    const double s = k == 0 ? v.w : fma(beta, v.s, v.w);
+    a.p[i] = p;
+    a.s[i] = s;
+    a.x[i] = fma(alpha, p, v.x);
+    const double r = fma(-alpha, s, v.r);
+    a.r[i] = r;
+    a.u[i] = v.dinv * r;
+}
+
+// the stop test on r.r, the step scalars, and the vector updates
+__global__ __launch_bounds__(kB) void cg_update_kernel(CgArgs a, int k)
+{
+    // the rows of the first row block are loaded before the reduction, so
+    // that the two latencies overlap
+    const int done = a.sc->done;
+    const int4 h = a.A.rb[blockIdx.x];
+    const int i0 = h.x + (int)threadIdx.x;
+    RowVals v0{};
+    if (i0 < h.y) load_row(a, i0, v0);
+    if (done) return;
+    const int par = k & 1;
+    const int slot[4] = {P_G0 + par, P_DE, P_RR, P_G0 + (par ^ 1)};
+    double t[4];
+    sum_partials<4>(a.part, slot, gridDim.x, t);
+    const double gamma = t[0], delta = t[1], rr = t[2];
+    CgScalars* sc = a.sc;
+    if (rr <= sc->thresh) {  // r_k is small enough: x_k is the result
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->iters = k;
+            sc->done = 1;
+        }
+        return;
+    }
+    double alpha, beta = 0.0;
+    if (k == 0) {
+        alpha = gamma / delta;
+    } else {
+        beta = gamma / t[3];
+        alpha = gamma / (delta - beta * gamma / sc->alpha[par ^ 1]);
+    }
+    if (!(alpha > 0.0) || !isfinite(alpha)) {  // E is not positive definite, or NaN
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->iters = k;
+            sc->done = 2;
+        }
+        return;
+    }
+    if (i0 < h.y) update_row(a, i0, v0, k, alpha, beta);
+    for (int64_t blk = blockIdx.x + gridDim.x; blk < a.A.nrb; blk += gridDim.x) {
+        const int4 hb = a.A.rb[blk];
+        const int i = hb.x + (int)threadIdx.x;
+        if (i >= hb.y) continue;
+        RowVals v;
+        load_row(a, i, v);
+        update_row(a, i, v, k, alpha, beta);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->alpha[par] = alpha;
+        sc->beta = beta;
+        sc->rr = rr;
+        sc->iters = k + 1;
+    }
 }
 
 inline unsigned grid_of(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
-inline unsigned red_grid(int64_t n)
-{
-    const int64_t g = (n + kB - 1) / kB;
-    return (unsigned)(g < kRedBlocks ? (g > 0 ? g : 1) : kRedBlocks);
-}
+// grid of the reducing kernels: one block per row block, at most kMaxRedBlocks
+inline int red_grid(int64_t nrb) { return (int)(nrb < kMaxRedBlocks ? (nrb > 0 ? nrb : 1) : kMaxRedBlocks); }
 
 }  // namespace
 
@@ -508,32 +600,33 @@ hipError_t launch_build_e(int64_t N, const int32_t* rp, const int32_t* ci, const
     return hipGetLastError();
 }
 
-hipError_t launch_spmv(int64_t N, const int32_t* rp, const int32_t* ci, const double* v, const double* x, double* y,
-                       hipStream_t s)
+hipError_t launch_spmv(const Csr& A, const double* v, const double* x, double* y, hipStream_t s)
 {
-    if (N <= 0) return hipSuccess;
-    spmv_kernel<<<grid_of(N), kB, 0, s>>>(N, rp, ci, v, x, y);
+    if (A.nrb <= 0) return hipSuccess;
+    spmv_kernel<<<(unsigned)A.nrb, kB, 0, s>>>(A, v, x, y);
     return hipGetLastError();
 }
 
 hipError_t launch_rhs(const RhsArgs& a, hipStream_t s)
 {
-    if (a.N <= 0) return hipSuccess;
-    rhs_kernel<<<grid_of(a.N), kB, 0, s>>>(a);
+    if (a.A.nrb <= 0) return hipSuccess;
+    rhs_kernel<<<(unsigned)a.A.nrb, kB, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_init(const CgArgs& a, hipStream_t s)
 {
-    cg_init_kernel<<<red_grid(a.N), kB, 0, s>>>(a);
+    const int G = red_grid(a.A.nrb);
+    cg_init_kernel<<<G, kB, 0, s>>>(a);
+    cg_start_kernel<<<1, kB, 0, s>>>(a, G);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_iteration(const CgArgs& a, hipStream_t s)
+hipError_t launch_cg_iteration(const CgArgs& a, int k, hipStream_t s)
 {
-    cg_spmv_kernel<<<red_grid(a.N), kB, 0, s>>>(a);
-    cg_update_kernel<<<red_grid(a.N), kB, 0, s>>>(a);
-    cg_direction_kernel<<<grid_of(a.N), kB, 0, s>>>(a);
+    const int G = red_grid(a.A.nrb);
+    cg_spmv_kernel<<<G, kB, 0, s>>>(a, k & 1);
+    cg_update_kernel<<<G, kB, 0, s>>>(a, k);
     return hipGetLastError();
 }
 

@@ -207,3 +207,46 @@ def test_table4_smallest_row_matches_oracle_run():
     h0g, epg, _, _ = run_table4_gpu(4, 1e-3)
     h0o, epo, _ = run_table4(O, 4, 1e-3)
     assert abs(h0g - h0o) <= 1e-7 * h0o and abs(epg - epo) <= 1e-7 * max(abs(epo), 1e-3)
+
+
+def _hill_at(hill, x, t_centre, t_spread):
+    """the hill centred where it is at t_centre, spread as at t_spread"""
+    c1, c2 = hill.centre(t_centre)
+    r2 = (x[:, 0] - c1) ** 2 + (x[:, 1] - c2) ** 2
+    s = 4.0 * t_spread * hill.kappa
+    return torch.exp(-r2 / s) / (math.pi * s)
+
+
+@pytest.mark.parametrize("kappa", [1e-3, 1e-5])
+def test_strang_splitting_alg2(kappa):
+    """Alg. 2: half a diffusion step, the advection step, half a diffusion
+    step.  Rotation and diffusion commute for this problem, so the exact
+    intermediate state after the first half step is the hill at its old
+    place spread by tau / 2 more; that gives the Dirichlet data of the first
+    half.  As the paper reports for this benchmark, the splitting changes the
+    H0 error little (here: within 20% of the unsplit scheme)."""
+    level = 5
+    h0_plain = run_table4_gpu(level, kappa)[0]
+    wl = W.annulus2d(level=level, kappa=kappa)
+    tr = mmoc.Tracer.from_workload(wl)
+    xt = tr.dof_coords().t().contiguous()
+    hill = wl.extra["hill"]
+    tr.set_stationary(True)
+    tr.set_velocity(0, wl.velocity(xt).t().contiguous())
+    c = hill(xt, hill.t0).contiguous()
+    a, b = torch.empty_like(c), torch.empty_like(c)
+    half = 0.5 * wl.dt
+    for k in range(wl.steps):
+        tn = hill.t0 + k * wl.dt
+        a, info = tr.diffusion_step(c, half, kappa, 1.0, dirichlet=_hill_at(hill, xt, tn, tn + half).contiguous(),
+                                    out=a)
+        assert info["converged"] == 1
+        tr.set_scalar(a)
+        tr.trace_step(wl.dt, wl.substeps, c_hat=b, want_X=False)
+        c, info = tr.diffusion_step(b, half, kappa, 1.0, dirichlet=hill(xt, tn + wl.dt).contiguous(), out=c)
+        assert info["converged"] == 1
+    ex = hill(xt, hill.t0 + wl.steps * wl.dt)
+    e = (ex - c).contiguous()
+    h0 = math.sqrt(float((e * tr.fe_apply(mmoc.MMOC_MAT_MASS, e)).sum()))
+    print("Strang kappa=%g: H0 %.3e, unsplit %.3e" % (kappa, h0, h0_plain))
+    assert abs(h0 / h0_plain - 1) < 0.2
