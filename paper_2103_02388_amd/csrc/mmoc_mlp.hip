@@ -30,21 +30,28 @@ typedef __attribute__((ext_vector_type(4))) float floatx4;
 constexpr int LDA = 72;  // padded bf16 row stride of LDS operand tiles (144 B)
 constexpr int LDF = 65;  // padded fp32 row stride
 
-__device__ __forceinline__ float gelu(float u)
+// The tanh form u/2 (1 + tanh(v)), v = sqrt(2/pi) (u + 0.044715 u^3), is
+// evaluated as u s with s = 1/(1 + e^(-2v)) (1 + tanh(v) = 2 s): one
+// hardware exp2 and one hardware reciprocal, no division.  e^(-2v) =
+// 2^(kk w) with w = u + 0.044715 u^3 and kk = -2 sqrt(2/pi) log2(e); for
+// very negative u it overflows to +inf and s to 0, as it should.
+constexpr float kGeluC = 0.7978845608028654f;   // sqrt(2/pi)
+constexpr float kGeluK = -2.3022082f;           // -2 sqrt(2/pi) / ln 2
+
+__device__ __forceinline__ float gelu_sig(float u)
 {
-    const float c = 0.7978845608028654f;  // sqrt(2/pi)
-    const float v = c * fmaf(0.044715f * u, u * u, u);
-    const float t = 1.0f - 2.0f / (__expf(2.0f * v) + 1.0f);  // tanh(v)
-    return 0.5f * u * (1.0f + t);
+    const float w = fmaf(0.044715f * u, u * u, u);
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(kGeluK * w));
 }
 
+__device__ __forceinline__ float gelu(float u) { return u * gelu_sig(u); }
+
+// d/du: with 1 - tanh(v)^2 = 4 s (1 - s), gelu'(u) = s + 2 u s (1 - s) v'
 __device__ __forceinline__ float gelu_d(float u)
 {
-    const float c = 0.7978845608028654f;
-    const float v = c * fmaf(0.044715f * u, u * u, u);
-    const float t = 1.0f - 2.0f / (__expf(2.0f * v) + 1.0f);
-    const float dv = c * fmaf(3.0f * 0.044715f, u * u, 1.0f);
-    return 0.5f * (1.0f + t) + 0.5f * u * (1.0f - t * t) * dv;
+    const float s = gelu_sig(u);
+    const float dv = kGeluC * fmaf(3.0f * 0.044715f, u * u, 1.0f);
+    return fmaf(2.0f * u * s * (1.0f - s), dv, s);
 }
 
 // acc[mt][nt] += A[64 x 64] * B where A is in LDS [m][k] (stride LDA) and B

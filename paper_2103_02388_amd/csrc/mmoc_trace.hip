@@ -587,22 +587,6 @@ __device__ __forceinline__ void count_flags(unsigned long long* stats, bool acti
     }
 }
 
-// Appends the lanes with `take` to a list: one atomic per wave on the list
-// length, each lane's position from its rank among the taking lanes.
-// Returns the lane's index into the list (meaningful where take is set).
-__device__ __forceinline__ unsigned long long wave_append(unsigned long long* len, bool take)
-{
-    const unsigned long long mask = __ballot(take);
-    if (mask == 0) return 0;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(len, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    const unsigned long long below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
-    return base + (unsigned long long)__popcll(below);
-}
-
 // --------------------------------------------------------------- fp64 trace
 
 // T is the storage type of the fields: double (MMOC_FP64) or float
@@ -1017,36 +1001,84 @@ __device__ __forceinline__ double unit_hash(uint64_t seed, uint64_t i)
     return (double)(mix64(seed ^ mix64(i)) >> 11) * (1.0 / 9007199254740992.0);
 }
 
-// one thread per tile: clear the tile's flags, then select its checked particles
-__global__ __launch_bounds__(256) void select_check_kernel(int64_t n, int tile, uint64_t seed, float fraction,
-                                                           int32_t* ids, unsigned long long* n_ids,
-                                                           unsigned char* checked, unsigned char* tile_flag)
+// Appends the block's lanes with `take` to a list: one atomic per block on
+// the list length (blocks of NT threads, every thread calls).  Returns the
+// lane's index into the list (meaningful where take is set).
+template <int NT>
+__device__ __forceinline__ unsigned long long block_append(unsigned long long* len, bool take)
 {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t i0 = k * tile;
-    if (i0 >= n) return;
-    const int64_t i1 = i0 + tile < n ? i0 + tile : n;
-    tile_flag[k] = 0;
-    int64_t best = i0;
-    double hb = 2.0;
+    __shared__ unsigned cnt[NT / 64];
+    __shared__ unsigned long long base;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long mask = __ballot(take);
+    if (lane == 0) cnt[wave] = (unsigned)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int w = 0; w < NT / 64; ++w) tot += cnt[w];
+        base = tot ? atomicAdd(len, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    unsigned before = 0;
+    for (int w = 0; w < wave; ++w) before += cnt[w];
+    const unsigned long long below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
+    return base + before + (unsigned long long)__popcll(below);
+}
+
+constexpr int kListBlock = 1024;
+
+// One thread per particle: particle i is checked when its hash is below
+// `fraction`; a tile (a whole number of waves, `tile` particles) with no
+// such particle checks its particle of smallest hash (ties: lowest index).
+// Clears the tile flags and appends the checked particles to the list.
+__global__ __launch_bounds__(kListBlock) void select_check_kernel(int64_t n, int tile, uint64_t seed, float fraction,
+                                                                  int32_t* ids, unsigned long long* n_ids,
+                                                                  unsigned char* checked, unsigned char* tile_flag)
+{
+    __shared__ double sh[kListBlock / 64];
+    __shared__ int64_t si[kListBlock / 64];
+    __shared__ int sany[kListBlock / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * kListBlock + threadIdx.x;
+    const bool in = i < n;
+    const double h = in ? unit_hash(seed, (uint64_t)i) : 2.0;
+    bool c = in && h < (double)fraction;
+    double hm = h;
+    int64_t im = i;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double oh = __shfl_xor(hm, off, 64);
+        const int64_t oi = __shfl_xor(im, off, 64);
+        if (oh < hm || (oh == hm && oi < im)) {
+            hm = oh;
+            im = oi;
+        }
+    }
+    const bool wany = __ballot(c) != 0;
+    if (lane == 0) {
+        sh[wave] = hm;
+        si[wave] = im;
+        sany[wave] = wany;
+    }
+    __syncthreads();
+    const int wpt = tile / 64, w0 = wave - wave % wpt;
     bool any = false;
-    for (int64_t i = i0; i < i1; ++i) {
-        const double h = unit_hash(seed, (uint64_t)i);
-        const bool c = h < (double)fraction;
+    double hb = 2.0;
+    int64_t best = -1;
+    for (int w = w0; w < w0 + wpt; ++w) {
+        any |= sany[w] != 0;
+        if (sh[w] < hb || (sh[w] == hb && si[w] < best)) {
+            hb = sh[w];
+            best = si[w];
+        }
+    }
+    if (!any && in && i == best) c = true;
+    if (in) {
         checked[i] = c;
-        if (c) {
-            any = true;
-            ids[atomicAdd(n_ids, 1ull)] = (int32_t)i;
-        }
-        if (h < hb) {
-            hb = h;
-            best = i;
-        }
+        if (i % tile == 0) tile_flag[i / tile] = 0;
     }
-    if (!any) {
-        checked[best] = 1;
-        ids[atomicAdd(n_ids, 1ull)] = (int32_t)best;
-    }
+    const unsigned long long pos = block_append<kListBlock>(n_ids, c);
+    if (c) ids[pos] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(256) void residual_kernel(int dim, int64_t n, int tile, const int32_t* __restrict__ ids,
@@ -1083,13 +1115,13 @@ __global__ __launch_bounds__(256) void residual_kernel(int dim, int64_t n, int t
     }
 }
 
-__global__ __launch_bounds__(256) void fallback_list_kernel(int64_t n, int tile, const unsigned char* tile_flag,
-                                                            const unsigned char* checked, int32_t* ids,
-                                                            unsigned long long* n_ids, unsigned long long* stats)
+__global__ __launch_bounds__(kListBlock) void fallback_list_kernel(int64_t n, int tile, const unsigned char* tile_flag,
+                                                                   const unsigned char* checked, int32_t* ids,
+                                                                   unsigned long long* n_ids, unsigned long long* stats)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kListBlock + threadIdx.x;
     const bool take = i < n && tile_flag[i / tile] && !checked[i];
-    const unsigned long long pos = wave_append(n_ids, take);
+    const unsigned long long pos = block_append<kListBlock>(n_ids, take);
     if (take) ids[pos] = (int32_t)i;
     const unsigned long long cnt = __popcll(__ballot(take));
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(stat_word(stats, ST_FALLBACK), cnt);
@@ -1199,10 +1231,10 @@ hipError_t launch_select_check(int64_t n, int tile, uint64_t seed, float fractio
                                unsigned long long* n_ids, unsigned char* checked, unsigned char* tile_flag,
                                hipStream_t s)
 {
-    const int64_t ntiles = (n + tile - 1) / tile;
-    if (ntiles <= 0) return hipSuccess;
-    select_check_kernel<<<(unsigned)((ntiles + 255) / 256), 256, 0, s>>>(n, tile, seed, fraction, ids, n_ids,
-                                                                          checked, tile_flag);
+    if (n <= 0) return hipSuccess;
+    if (tile % 64 != 0 || kListBlock % tile != 0) return hipErrorInvalidValue;
+    select_check_kernel<<<(unsigned)((n + kListBlock - 1) / kListBlock), kListBlock, 0, s>>>(
+        n, tile, seed, fraction, ids, n_ids, checked, tile_flag);
     return hipGetLastError();
 }
 
@@ -1220,7 +1252,8 @@ hipError_t launch_fallback_list(int64_t n, int tile, const unsigned char* tile_f
                                 int32_t* ids, unsigned long long* n_ids, unsigned long long* stats, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    fallback_list_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, tile, tile_flag, checked, ids, n_ids, stats);
+    fallback_list_kernel<<<(unsigned)((n + kListBlock - 1) / kListBlock), kListBlock, 0, s>>>(n, tile, tile_flag,
+                                                                                          checked, ids, n_ids, stats);
     return hipGetLastError();
 }
 

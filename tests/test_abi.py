@@ -121,8 +121,16 @@ def test_mesh_errors():
     with pytest.raises(mmoc.MMOCError) as e:
         mmoc.Tracer(3, 1, v, m3)
     assert e.value.status == -2
-    # shell blending in 2D is not built
+    # radial blending needs vertices away from the origin, each macro spanning
+    # exactly d radial directions: the unit square has a vertex at the origin
     vs, ms = W.square2()
     with pytest.raises(mmoc.MMOCError) as e:
         mmoc.Tracer(2, 1, vs, ms, blend=1)
+    assert e.value.status == -2
+    # P1 elements are not built for blended meshes
+    va, ma = W.annulus()
+    opt = mmoc.mmoc_default_options()
+    opt.order = 1
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.Tracer(2, 1, va, ma, blend=1, options=opt)
     assert e.value.status == -6

@@ -223,8 +223,11 @@ def test_strang_splitting_alg2(kappa):
     step.  Rotation and diffusion commute for this problem, so the exact
     intermediate state after the first half step is the hill at its old
     place spread by tau / 2 more; that gives the Dirichlet data of the first
-    half.  As the paper reports for this benchmark, the splitting changes the
-    H0 error little (here: within 20% of the unsplit scheme)."""
+    half.  At kappa = 1e-5 the error is the advection error and the
+    splitting leaves it within 2% (the paper reports no relevant difference
+    on this benchmark).  At kappa = 1e-3 the error is implicit Euler's time
+    error, and two half steps halve it: the split run is never worse and at
+    least a third of the unsplit error."""
     level = 5
     h0_plain = run_table4_gpu(level, kappa)[0]
     wl = W.annulus2d(level=level, kappa=kappa)
@@ -249,4 +252,7 @@ def test_strang_splitting_alg2(kappa):
     e = (ex - c).contiguous()
     h0 = math.sqrt(float((e * tr.fe_apply(mmoc.MMOC_MAT_MASS, e)).sum()))
     print("Strang kappa=%g: H0 %.3e, unsplit %.3e" % (kappa, h0, h0_plain))
-    assert abs(h0 / h0_plain - 1) < 0.2
+    if kappa <= 1e-5:
+        assert abs(h0 / h0_plain - 1) < 0.02
+    else:
+        assert h0_plain / 3 < h0 <= h0_plain
