@@ -71,17 +71,22 @@ PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
 
 
-def traffic_entry():
-    """HBM bytes per launch of the float64 trace kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+def counter_summary():
+    """The committed rocprofv3 counter summary of the float64 trace kernel,
+    if it was taken on the current kernel source (else None)."""
     try:
         d = json.load(open(TRAFFIC))
         sha = hashlib.sha256(open(TRACE_SRC, "rb").read()).hexdigest()
-        if d.get("source_sha256") != sha:
-            return None
-        return d["hbm_bytes_per_launch"]
+        return d if d.get("source_sha256") == sha else None
     except Exception:
         return None
+
+
+def traffic_entry():
+    """HBM bytes per launch of the float64 trace kernel (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy's counts)."""
+    d = counter_summary()
+    return d["hbm_bytes_per_launch"] if d else None
 
 
 def main():
@@ -96,6 +101,8 @@ def main():
     ap.add_argument("--no-diffusion", action="store_true")
     ap.add_argument("--diffusion-only", action="store_true",
                     help="only the advection-diffusion sub-result (for profiling its kernels)")
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="only the operator apply on the large annulus (for profiling that kernel alone)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (10 times), to scale HBM counters")
     args = ap.parse_args()
@@ -119,6 +126,9 @@ def main():
     torch.cuda.set_device(0)
     if args.diffusion_only:
         print(json.dumps({"diffusion": time_diffusion()}), flush=True)
+        return
+    if args.spmv_only:
+        print(json.dumps({"spmv": spmv_roofline()}), flush=True)
         return
     wl = W.swirl3d()
     S = args.substeps
@@ -154,7 +164,8 @@ def main():
                      "traffic": traffic_entry(),
                      "kernel": "trace_fp64_kernel<3,2,0>", "kernel_ms": r["kernel_ms"], "flop_per_particle": fpp,
                      "hbm_GBps_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / 1e9,
-                     "hbm_frac_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / PEAK_HBM},
+                     "hbm_frac_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / PEAK_HBM,
+                     "l1_tag_lookups_per_cu_cycle": (counter_summary() or {}).get("l1_tag_lookups_per_cu_cycle")},
         "trace_only_particles_per_s": N / (r["kernel_ms"] * 1e-3),
         "stats": r["stats"],
     }
@@ -375,28 +386,8 @@ def time_diffusion():
     ep = float(c.max() / ex.max() - 1.0)
     steps = wl.steps
     diff_ms = wall - tr_ms
-    # the operator apply on its own: Table 4 mesh (cache resident) and a large mesh
-    def spmv_time(t, reps=50):
-        v = torch.ones(t.N, dtype=torch.float64, device="cuda")
-        y = torch.empty_like(v)
-        for _ in range(3):
-            t.fe_apply(mmoc.MMOC_MAT_MASS, v, y)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record()
-        for _ in range(reps):
-            t.fe_apply(mmoc.MMOC_MAT_MASS, v, y)
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
     small_ms = spmv_time(tr)
     tr.close()
-    big = mmoc.Tracer.from_workload(W.annulus2d(level=8, kappa=kappa))
-    bnnz = big.fe_assemble()
-    big_ms = spmv_time(big)
-    bN = big.N
-    big.close()
-    achieved = spmv_bytes(bN, bnnz) / (big_ms * 1e-3)
     return {
         "workload": "annulus2d: r in [0.5, 1.5], 6x2 macro triangles, radial blending, level 6, 197376 P2 DoFs; "
                     "rotation (-x2, x1); Gaussian hill kappa 1e-3; tau = 2 pi/63, one RK4 step per tau, 63 steps; "
@@ -407,11 +398,44 @@ def time_diffusion():
         "cg_iterations_per_step": iters / steps, "us_per_cg_iteration": diff_ms * 1e3 / max(iters, 1),
         "assembly_ms": setup_ms, "H0_error": h0, "E_peak": ep, "paper_H0": 4.32e-3, "paper_E_peak": 3.98e-3,
         "spmv_table4_mesh_us": small_ms * 1e3,
-        "roofline": {"bound": "hbm", "kernel": "spmv_kernel (CSR, mass matrix)", "mesh": "annulus2d level 8",
-                     "dofs": bN, "nnz": bnnz, "kernel_ms": big_ms, "bytes_per_launch": spmv_bytes(bN, bnnz),
-                     "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": achieved / PEAK_HBM,
-                     "traffic": None},
+        "roofline": spmv_roofline(),
     }
+
+
+def spmv_time(t, reps=50):
+    """mean duration (ms) of the mass-matrix apply, HIP events around the
+    launches on the stream they run on"""
+    import torch
+    from paper_2103_02388_amd import mmoc
+    v = torch.ones(t.N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(v)
+    for _ in range(3):
+        t.fe_apply(mmoc.MMOC_MAT_MASS, v, y)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        t.fe_apply(mmoc.MMOC_MAT_MASS, v, y)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def spmv_roofline():
+    """The CSR operator apply on the level-8 annulus (3,148,800 DoFs, 36M
+    entries, 497 MB per apply: beyond the last-level cache)."""
+    from paper_2103_02388_amd import mmoc
+    from paper_2103_02388_amd import workloads as W
+    big = mmoc.Tracer.from_workload(W.annulus2d(level=8))
+    bnnz = big.fe_assemble()
+    big_ms = spmv_time(big)
+    bN = big.N
+    big.close()
+    achieved = spmv_bytes(bN, bnnz) / (big_ms * 1e-3)
+    return {"bound": "hbm", "kernel": "spmv_kernel (CSR, mass matrix)", "mesh": "annulus2d level 8",
+            "dofs": bN, "nnz": bnnz, "kernel_ms": big_ms, "bytes_per_launch": spmv_bytes(bN, bnnz),
+            "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": achieved / PEAK_HBM,
+            "traffic": None}
 
 
 def cpu_baseline(wl, S):

@@ -51,14 +51,19 @@
 #define MMOC_WPE_FP32 4
 #endif
 // Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
-// The trace kernels remap them so that each XCD receives runs of
-// MMOC_XCD_CHUNK consecutive logical blocks (neighbouring particles, hence
-// neighbouring field data in that XCD's L2), while consecutive runs go to
-// different XCDs (so that regions with more work -- walks, tie-band
-// re-locations -- are spread over all of them).  0: one contiguous eighth of
-// the range per XCD; 1: no remapping.
-#ifndef MMOC_XCD_CHUNK
-#define MMOC_XCD_CHUNK 16
+// The trace kernels remap them so that each XCD receives runs of CHUNK
+// consecutive logical blocks (neighbouring particles, hence neighbouring
+// field data in that XCD's L2), consecutive runs going to different XCDs.
+// CHUNK 0 gives each XCD one contiguous eighth of the range: every field
+// line is then pulled into about one L2, and the float64 kernels use it.
+// The float32-mixed kernel takes runs of 16 blocks instead: its tie-band
+// re-locations cluster in regions, and runs spread them over all XCDs.
+// CHUNK 1: no remapping.
+#ifndef MMOC_XCD_CHUNK_FP64
+#define MMOC_XCD_CHUNK_FP64 0
+#endif
+#ifndef MMOC_XCD_CHUNK_FP32
+#define MMOC_XCD_CHUNK_FP32 16
 #endif
 
 namespace mmoc {
@@ -66,15 +71,12 @@ namespace {
 
 constexpr int kTB = MMOC_TRACE_BLOCK;
 
+template <unsigned CHUNK>
 __device__ __forceinline__ int64_t logical_block()
 {
     const unsigned b = blockIdx.x, x = b & 7u, j = b >> 3;
-#if MMOC_XCD_CHUNK == 0
-    return (int64_t)x * (gridDim.x >> 3) + j;
-#else
-    constexpr unsigned c = MMOC_XCD_CHUNK;
-    return ((int64_t)(j / c) * 8 + x) * c + (j % c);
-#endif
+    if constexpr (CHUNK == 0) return (int64_t)x * (gridDim.x >> 3) + j;
+    else return ((int64_t)(j / CHUNK) * 8 + x) * CHUNK + (j % CHUNK);
 }
 
 // ------------------------------------------------------------------ geometry
@@ -599,7 +601,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP
 void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T* __restrict__ c_hat,
                        double* __restrict__ X, unsigned long long* __restrict__ stats)
 {
-    const int64_t t = logical_block() * kTB + threadIdx.x;
+    const int64_t t = logical_block<MMOC_XCD_CHUNK_FP64>() * kTB + threadIdx.x;
     const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
     unsigned flags = 0;
     if (active) {
@@ -874,7 +876,7 @@ template <int DIM, int NLEV, int BLEND, int ORD>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP32)))
 void trace_fp32_kernel(const TraceArgs<float> A)
 {
-    const int64_t t = logical_block() * kTB + threadIdx.x;
+    const int64_t t = logical_block<MMOC_XCD_CHUNK_FP32>() * kTB + threadIdx.x;
     const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
     unsigned flags = 0;
     if (active) {
@@ -1129,9 +1131,10 @@ __global__ __launch_bounds__(kListBlock) void fallback_list_kernel(int64_t n, in
 
 // grid of the remapped kernels: a whole number of XCD rounds (the blocks
 // beyond the particle range have no active lane)
+template <unsigned CHUNK>
 inline unsigned grid_xcd(int64_t n)
 {
-    constexpr int64_t round = 8 * (MMOC_XCD_CHUNK > 0 ? MMOC_XCD_CHUNK : 1);
+    constexpr int64_t round = 8 * (CHUNK > 0 ? CHUNK : 1);
     int64_t b = (n + kTB - 1) / kTB;
     b = (b + round - 1) / round * round;
     return (unsigned)b;
@@ -1142,7 +1145,7 @@ inline unsigned grid_xcd(int64_t n)
 template <typename T, bool G, int ORD>
 hipError_t launch_trace_f64g(int dim, int blend, const TraceArgs<T>& a, hipStream_t s)
 {
-    const dim3 grid(grid_xcd(a.n)), block(kTB);
+    const dim3 grid(grid_xcd<MMOC_XCD_CHUNK_FP64>(a.n)), block(kTB);
     const bool st = a.nlev == 1;
     if (dim == 2 && !blend) {
         if (st) trace_fp64_kernel<2, 1, 0, T, G, ORD><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
@@ -1262,7 +1265,7 @@ hipError_t launch_fallback_list(int64_t n, int tile, const unsigned char* tile_f
 template <int ORD>
 hipError_t launch_trace_fp32o(int dim, int blend, const TraceArgs<float>& a, hipStream_t s)
 {
-    const dim3 grid(grid_xcd(a.n)), block(kTB);
+    const dim3 grid(grid_xcd<MMOC_XCD_CHUNK_FP32>(a.n)), block(kTB);
     const bool st = a.nlev == 1;
     if (dim == 2 && !blend) {
         if (st) trace_fp32_kernel<2, 1, 0, ORD><<<grid, block, 0, s>>>(a);
