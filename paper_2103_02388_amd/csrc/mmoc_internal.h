@@ -102,6 +102,7 @@ struct TraceArgs {
     int lat_m;               // DoF lattice resolution, order * level_n
     int substeps;            // RK sub-steps per interval (dt = interval length)
     int max_hops;
+    int xcd_log2;            // set by the launcher: log2 of the XCD run length in blocks, -1 contiguous eighths
     double dt;
     double eps_in;
     float eps32_macro;
