@@ -570,6 +570,21 @@ __device__ __forceinline__ int own_lat_idx(uint64_t e)
     else return tet_n(I) + tri_n(J) + K;
 }
 
+// A particle at rest (zero velocity at its DoF, e.g. on a no-slip wall or a
+// stagnation line) evaluates at its own DoF again and again.  P2
+// interpolation at a node is the nodal value, so such an evaluation needs no
+// location and one nodal load instead of the stencil's gathers.  `home`
+// tracks Y == the DoF position (no departure-point update has changed a
+// bit of it); a stage point y is the DoF when home and y == Y.
+template <int DIM>
+__device__ __forceinline__ bool same_point(const double* y, const double* x)
+{
+    bool same = true;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) same &= y[i] == x[i];
+    return same;
+}
+
 // this block's word of statistic row `which`
 __device__ __forceinline__ unsigned long long* stat_word(unsigned long long* stats, int which)
 {
@@ -616,6 +631,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
         int M;
         double Y[DIM];
         dof_position<DIM, BLEND>(geo, e, A.lat_m, M, Y);
+        bool home = true;
         uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
         const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
         const double h = A.dt / (double)A.substeps;
@@ -660,8 +676,10 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                         }
                         double theta;
                         const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)j + A.rk.c[q]) * invS, theta);
-                        if (j == 0 && q == 0) nodal_vel<DIM, NLEV, T, double>(Lv, own_slot, theta, K[0]);
-                        else velocity(y, Lv, theta, K[q]);
+                        if ((j == 0 && q == 0) || (home && same_point<DIM>(y, Y)))
+                            nodal_vel<DIM, NLEV, T, double>(Lv, own_slot, theta, K[q]);
+                        else
+                            velocity(y, Lv, theta, K[q]);
                     }
                 }
 #pragma unroll
@@ -670,7 +688,9 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
 #pragma unroll
                     for (int q = 0; q < kMaxStages; ++q)
                         if (q < A.rk.s) sum = fma(A.rk.b[q], K[q][i], sum);
-                    Y[i] = Y[i] - h * sum;
+                    const double yn = Y[i] - h * sum;
+                    home = home && yn == Y[i];
+                    Y[i] = yn;
                 }
             }
         } else {
@@ -686,8 +706,8 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                     const double as = stg == 0 ? 0.0 : (stg == 3 ? 1.0 : 0.5);
                     double theta;
                     const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)j + as) * invS, theta);
-                    if (j == 0 && stg == 0) {
-                        // the particle sits on its own DoF
+                    if ((j == 0 && stg == 0) || (home && same_point<DIM>(y, Y))) {
+                        // the stage point is the particle's own DoF
                         nodal_vel<DIM, NLEV, T, double>(Lv, own_slot, theta, ks);
                     } else {
                         velocity(y, Lv, theta, ks);
@@ -702,23 +722,32 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                     }
                 }
 #pragma unroll
-                for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - h6 * acc[i];
+                for (int i = 0; i < DIM; ++i) {
+                    const double yn = Y[i] - h6 * acc[i];
+                    home = home && yn == Y[i];
+                    Y[i] = yn;
+                }
             }
         }
         // step (iii): the scalar at the departure point
-        l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
-        lmin = lam_min<DIM, double>(l0, s);
-        if (lmin < -A.eps_in) {
-            const unsigned r =
-                walk64<DIM, BLEND>(geo, A.nm, A.max_hops, A.eps_in, M, Y[0], Y[1], DIM == 3 ? Y[DIM - 1] : 0.0);
-            flags |= r >> 27;
-            M = (int)(r & ((1u << 27) - 1));
-            mbase = (uint32_t)M * (uint32_t)A.npm;
+        double v;
+        if (home) {
+            v = (double)ldv<T>(A.cs, own_slot * (uint32_t)sizeof(T));
+        } else {
             l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
             lmin = lam_min<DIM, double>(l0, s);
+            if (lmin < -A.eps_in) {
+                const unsigned r =
+                    walk64<DIM, BLEND>(geo, A.nm, A.max_hops, A.eps_in, M, Y[0], Y[1], DIM == 3 ? Y[DIM - 1] : 0.0);
+                flags |= r >> 27;
+                M = (int)(r & ((1u << 27) - 1));
+                mbase = (uint32_t)M * (uint32_t)A.npm;
+                l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
+                lmin = lam_min<DIM, double>(l0, s);
+            }
+            micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
+            v = gather_scalar<DIM, T, double>(A, mbase, st);
         }
-        micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
-        const double v = gather_scalar<DIM, T, double>(A, mbase, st);
         bool bad = v != v;
 #pragma unroll
         for (int i = 0; i < DIM; ++i) bad |= Y[i] != Y[i];
@@ -857,6 +886,23 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint
         }
         macro_redo = interior;
     }
+    if (macro_redo && lmin > -A.eps32_macro) {
+        // The float64 tie-break: the barycentrics of the current macro in
+        // float64.  Inside (the float64 walk would stay) -- the common case of
+        // a point on or next to an interior face -- the micro element follows
+        // from them; otherwise the full float64 re-location below walks.
+        double s64[DIM];
+        const double l064 = ref_at<DIM, BLEND>(A.geo, M, y, s64);
+        const double lmin64 = lam_min<DIM, double>(l064, s64);
+        if (lmin64 >= -A.eps_in) {
+            flags |= LF_TIEBAND;
+            float sf[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) sf[i] = (float)s64[i];
+            micro<DIM, float, false, ORD>(sf, (float)l064, (float)lmin64, A.level_n, st);
+            return;
+        }
+    }
     bool redo = macro_redo;
     if (!macro_redo) {
         if (A.eps32_micro > 0.0f) {
@@ -891,6 +937,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
         int M;
         double Y[DIM];
         dof_position<DIM, BLEND>(A.geo, e, A.lat_m, M, Y);
+        bool home = true;
         uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
         const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
         const double hd = A.dt / (double)A.substeps;
@@ -911,7 +958,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
                 const double as = stg == 0 ? 0.0 : (stg == 3 ? 1.0 : 0.5);
                 float theta;
                 const Levels<float> Lv = levels_at<NLEV, float, float>(A, ((double)j + as) * invSd, theta);
-                if (j == 0 && stg == 0) {
+                if ((j == 0 && stg == 0) || (home && same_point<DIM>(y, Y))) {
                     nodal_vel<DIM, NLEV, float, float>(Lv, own_slot, theta, ks);
                 } else {
                     locate32<DIM, BLEND, ORD>(A, M, mbase, y, st, flags);
@@ -927,10 +974,19 @@ void trace_fp32_kernel(const TraceArgs<float> A)
             }
             // departure point accumulated in float64
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) Y[i] = Y[i] - (double)(h6 * acc[i]);
+            for (int i = 0; i < DIM; ++i) {
+                const double yn = Y[i] - (double)(h6 * acc[i]);
+                home = home && yn == Y[i];
+                Y[i] = yn;
+            }
         }
-        locate32<DIM, BLEND, ORD>(A, M, mbase, Y, st, flags);
-        const float v = gather_scalar<DIM, float, float>(A, mbase, st);
+        float v;
+        if (home) {
+            v = ldv<float>(A.cs, own_slot * 4u);
+        } else {
+            locate32<DIM, BLEND, ORD>(A, M, mbase, Y, st, flags);
+            v = gather_scalar<DIM, float, float>(A, mbase, st);
+        }
         bool bad = v != v;
 #pragma unroll
         for (int i = 0; i < DIM; ++i) bad |= Y[i] != Y[i];
