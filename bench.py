@@ -222,13 +222,10 @@ def time_path(wl, path, S, steps, warmup):
             cur.copy_(c0)
         else:
             tr.swap_levels()
-        tr.set_velocity(1, U[n + 1])
-        # the scalar of this step: the initial condition, or the last step's
-        # result (float32 results are widened to float64 first)
-        if n == 0 or not same_dtype:
-            tr.set_scalar(cur)
-        else:
-            tr.set_scalar(chat)
+        # the new velocity level and the scalar of this step (the initial
+        # condition, or the last step's result; float32 results are widened
+        # to float64 first), in one ingestion pass
+        tr.set_fields(1, U[n + 1], cur if (n == 0 or not same_dtype) else chat)
         if ev is not None:
             ev[0].record()
         mmoc.mmoc_trace_step(tr.ctx, wl.dt, S, chat, X)

@@ -166,6 +166,12 @@ mmoc_status mmoc_swap_velocity_levels(mmoc_ctx* ctx);
  * (copied into the block layout). */
 mmoc_status mmoc_set_scalar(mmoc_ctx* ctx, const double* c_dev);
 
+/* mmoc_set_velocity(ctx, level, u_dev) and mmoc_set_scalar(ctx, c_dev) in
+ * one pass over the block layout: the field ingestion of a time step
+ * (Alg. 1: the new velocity level and the current scalar).  Same arguments,
+ * layouts and errors as the two calls. */
+mmoc_status mmoc_set_fields(mmoc_ctx* ctx, int level, const double* u_dev, const double* c_dev);
+
 /* One MMOC advection step of length dt > 0 with substeps >= 1 RK4 sub-steps
  * (Alg. 1 departure-point and advection lines).  c_hat_dev receives
  * chat_i = c_h^n(X_i) in unique order: double* [n_unique] for MMOC_FP64,

@@ -491,39 +491,71 @@ mmoc_status mmoc_dof_coords(mmoc_ctx* c, double* xyz)
     return MMOC_OK;
 }
 
-mmoc_status mmoc_set_velocity(mmoc_ctx* c, int level, const double* u)
+// the record elements of velocity level `level` (ring slot) for components
+// 0..dim-1 of u, appended to d from entry `first`
+static void velocity_dst(mmoc_ctx* c, int level, const double* u, mmoc::ScatterDst& d, int first)
 {
-    if (!c) return MMOC_E_ARG;
-    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
-    if (level < 0 || level >= c->lev_cap)
-        return fail(c, MMOC_E_ARG, "level must be in [0, %d] (the velocity levels held)", c->lev_cap - 1);
-    if (c->stationary && level != 0) return fail(c, MMOC_E_STATE, "stationary velocity: only level 0 is used");
-    mmoc_status st = check_dev(c, u, sizeof(double) * c->dim * c->N, 8, "u_dev");
-    if (st != MMOC_OK) return st;
     const int L = phys_level(c, level);
     const size_t elem = c->prec == MMOC_FP64 ? sizeof(double) : sizeof(float);
     void* va = static_cast<char*>(c->va_all) + (size_t)L * c->va_lstride * elem;
     void* vb = c->vb_all ? static_cast<char*>(c->vb_all) + (size_t)L * c->vb_lstride * elem : nullptr;
-    mmoc::ScatterDst d{};
+    for (int i = 0; i < c->dim; ++i) d.src[first + i] = u + (size_t)i * c->N;
     if (c->dim == 3 && c->prec == MMOC_FP64) {
-        d.dst[0] = d.dst[1] = va;
-        d.dst[2] = vb;
-        d.stride[0] = d.stride[1] = 2;
-        d.stride[2] = 1;
-        d.off[0] = 0;
-        d.off[1] = 1;
-        d.off[2] = 0;
+        d.dst[first] = d.dst[first + 1] = va;
+        d.dst[first + 2] = vb;
+        d.stride[first] = d.stride[first + 1] = 2;
+        d.stride[first + 2] = 1;
+        d.off[first] = 0;
+        d.off[first + 1] = 1;
+        d.off[first + 2] = 0;
     } else {
         const int na = c->dim == 3 ? 3 : 2;
         for (int i = 0; i < c->dim; ++i) {
-            d.dst[i] = va;
-            d.stride[i] = na;
-            d.off[i] = i;
+            d.dst[first + i] = va;
+            d.stride[first + i] = na;
+            d.off[first + i] = i;
         }
     }
-    HIPCHK(c, mmoc::launch_scatter(c->dim, c->slot_uid_d, c->nslots, u, c->N, d, c->prec != MMOC_FP64, c->stream),
+}
+
+static mmoc_status check_velocity_level(mmoc_ctx* c, int level, const double* u)
+{
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (level < 0 || level >= c->lev_cap)
+        return fail(c, MMOC_E_ARG, "level must be in [0, %d] (the velocity levels held)", c->lev_cap - 1);
+    if (c->stationary && level != 0) return fail(c, MMOC_E_STATE, "stationary velocity: only level 0 is used");
+    return check_dev(c, u, sizeof(double) * c->dim * c->N, 8, "u_dev");
+}
+
+mmoc_status mmoc_set_velocity(mmoc_ctx* c, int level, const double* u)
+{
+    if (!c) return MMOC_E_ARG;
+    mmoc_status st = check_velocity_level(c, level, u);
+    if (st != MMOC_OK) return st;
+    mmoc::ScatterDst d{};
+    velocity_dst(c, level, u, d, 0);
+    HIPCHK(c, mmoc::launch_scatter(c->dim, c->slot_uid_d, c->nslots, c->N, d, c->prec != MMOC_FP64, c->stream),
            "set_velocity");
     c->vel_set[level] = true;
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_set_fields(mmoc_ctx* c, int level, const double* u, const double* cs)
+{
+    if (!c) return MMOC_E_ARG;
+    mmoc_status st = check_velocity_level(c, level, u);
+    if (st != MMOC_OK) return st;
+    if ((st = check_dev(c, cs, sizeof(double) * c->N, 8, "c_dev")) != MMOC_OK) return st;
+    mmoc::ScatterDst d{};
+    velocity_dst(c, level, u, d, 0);
+    d.src[c->dim] = cs;
+    d.dst[c->dim] = c->cs_d;
+    d.stride[c->dim] = 1;
+    d.off[c->dim] = 0;
+    HIPCHK(c, mmoc::launch_scatter(c->dim + 1, c->slot_uid_d, c->nslots, c->N, d, c->prec != MMOC_FP64, c->stream),
+           "set_fields");
+    c->vel_set[level] = true;
+    c->scalar_set = true;
     return MMOC_OK;
 }
 
@@ -557,10 +589,11 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
     mmoc_status st = check_dev(c, cs, sizeof(double) * c->N, 8, "c_dev");
     if (st != MMOC_OK) return st;
     mmoc::ScatterDst d{};
+    d.src[0] = cs;
     d.dst[0] = c->cs_d;
     d.stride[0] = 1;
     d.off[0] = 0;
-    HIPCHK(c, mmoc::launch_scatter(1, c->slot_uid_d, c->nslots, cs, c->N, d, c->prec != MMOC_FP64, c->stream),
+    HIPCHK(c, mmoc::launch_scatter(1, c->slot_uid_d, c->nslots, c->N, d, c->prec != MMOC_FP64, c->stream),
            "set_scalar");
     c->scalar_set = true;
     return MMOC_OK;

@@ -129,13 +129,16 @@ hipError_t launch_dof_coords(int dim, int blend, const MacroGeo* geo, const uint
                              int64_t n, int lat_m, double* out, hipStream_t s);
 // Copy of a unique-layout field into block slots: component i of DoF
 // slot_uid[slot] goes to dst[i][slot * stride[i] + off[i]] (i < ncomp).
+// Field ingestion: component i of the unique array src[i] (n_unique values)
+// goes to record element dst[i][slot * stride[i] + off[i]] of every slot.
 struct ScatterDst {
-    void* dst[3];
-    int stride[3];
-    int off[3];
+    const double* src[4];
+    void* dst[4];
+    int stride[4];
+    int off[4];
 };
-hipError_t launch_scatter(int ncomp, const int32_t* slot_uid, int64_t nslots, const double* u, int64_t n_unique,
-                          const ScatterDst& d, int fp32, hipStream_t s);
+hipError_t launch_scatter(int ncomp, const int32_t* slot_uid, int64_t nslots, int64_t n_unique, const ScatterDst& d,
+                          int fp32, hipStream_t s);
 
 // P2 mass matrix of a simplex of unit volume, nodes ordered as vertices
 // 0..d then edges (a, b), a < b, lexicographic; entry (i, j) at m[i * NN + j]

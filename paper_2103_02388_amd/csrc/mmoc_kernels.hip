@@ -55,14 +55,13 @@ __global__ __launch_bounds__(kBlock) void dof_coords_kernel(const MacroGeo* __re
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void scatter_kernel(int ncomp, const int32_t* __restrict__ slot_uid,
-                                                         int64_t nslots, const double* __restrict__ u, int64_t nu,
-                                                         ScatterDst d)
+                                                         int64_t nslots, int64_t nu, ScatterDst d)
 {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= nslots) return;
     const int64_t q = slot_uid[t];
-    for (int i = 0; i < ncomp; ++i)
-        static_cast<T*>(d.dst[i])[t * d.stride[i] + d.off[i]] = (T)u[(int64_t)i * nu + q];
+    for (int i = 0; i < ncomp; ++i) static_cast<T*>(d.dst[i])[t * d.stride[i] + d.off[i]] = (T)d.src[i][q];
+    (void)nu;
 }
 
 inline unsigned grid_plain(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -81,13 +80,14 @@ hipError_t launch_dof_coords(int dim, int blend, const MacroGeo* geo, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(int ncomp, const int32_t* slot_uid, int64_t nslots, const double* u, int64_t n_unique,
-                          const ScatterDst& d, int fp32, hipStream_t s)
+hipError_t launch_scatter(int ncomp, const int32_t* slot_uid, int64_t nslots, int64_t n_unique, const ScatterDst& d,
+                          int fp32, hipStream_t s)
 {
     if (nslots <= 0) return hipSuccess;
+    if (ncomp < 1 || ncomp > 4) return hipErrorInvalidValue;
     const dim3 grid(grid_plain(nslots)), block(kBlock);
-    if (fp32) scatter_kernel<float><<<grid, block, 0, s>>>(ncomp, slot_uid, nslots, u, n_unique, d);
-    else scatter_kernel<double><<<grid, block, 0, s>>>(ncomp, slot_uid, nslots, u, n_unique, d);
+    if (fp32) scatter_kernel<float><<<grid, block, 0, s>>>(ncomp, slot_uid, nslots, n_unique, d);
+    else scatter_kernel<double><<<grid, block, 0, s>>>(ncomp, slot_uid, nslots, n_unique, d);
     return hipGetLastError();
 }
 

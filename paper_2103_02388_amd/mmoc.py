@@ -38,6 +38,7 @@ EXPORTED = [
     "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad", "mmoc_mass_inner", "mmoc_field_range",
     "mmoc_lookback_run", "mmoc_set_rk_tableau", "mmoc_cfl_time_step", "mmoc_set_level_count", "mmoc_trace_span",
     "mmoc_fe_assemble", "mmoc_fe_export", "mmoc_fe_apply", "mmoc_boundary_mask", "mmoc_diffusion_step",
+    "mmoc_set_fields",
 ]
 
 
@@ -98,6 +99,7 @@ def lib():
         "mmoc_set_stationary": (st, [P, I]),
         "mmoc_swap_velocity_levels": (st, [P]),
         "mmoc_set_scalar": (st, [P, P]),
+        "mmoc_set_fields": (st, [P, I, P, P]),
         "mmoc_trace_step": (st, [P, D, I, P, P]),
         "mmoc_get_stats": (st, [P, C.POINTER(mmoc_stats)]),
         "mmoc_reset_stats": (st, [P]),
@@ -204,6 +206,10 @@ def mmoc_swap_velocity_levels(ctx):
 
 def mmoc_set_scalar(ctx, c: torch.Tensor):
     _check(ctx, lib().mmoc_set_scalar(ctx, _ptr(c)))
+
+
+def mmoc_set_fields(ctx, level, u: torch.Tensor, c: torch.Tensor):
+    _check(ctx, lib().mmoc_set_fields(ctx, int(level), _ptr(u), _ptr(c)))
 
 
 def mmoc_trace_step(ctx, dt, substeps, c_hat: torch.Tensor, X: Optional[torch.Tensor]):
@@ -418,6 +424,10 @@ class Tracer:
 
     def set_scalar(self, c):
         mmoc_set_scalar(self.ctx, c)
+
+    def set_fields(self, level, u, c):
+        """velocity level and scalar in one ingestion pass"""
+        mmoc_set_fields(self.ctx, level, u, c)
 
     def swap_levels(self):
         mmoc_swap_velocity_levels(self.ctx)

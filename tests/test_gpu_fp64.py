@@ -208,3 +208,27 @@ def test_plume3d_full_size_sampled():
     chr_, Xr, _ = p.oracle_step(wl.dt, 4, ids=ids, threads=8)
     ex, ec = rel_x(X[:, ids], Xr), rel_c(ch[ids], chr_)
     assert ex <= TOL and ec <= TOL
+
+
+@pytest.mark.parametrize("prec", [mmoc.MMOC_FP64, mmoc.MMOC_FP32_FIELDS])
+def test_set_fields_equals_separate_calls(prec):
+    """mmoc_set_fields (velocity level and scalar in one pass) gives the
+    same step, bit for bit, as mmoc_set_velocity + mmoc_set_scalar."""
+    wl = W.swirl3d()
+    out = []
+    for combined in (False, True):
+        p = Pair(wl, level=3, precision=prec)
+        u0 = field_gpu(wl.velocity, p.xg, 0.4)
+        u1 = field_gpu(wl.velocity, p.xg, 0.4 + wl.dt)
+        c = field_gpu(wl.scalar0, p.xg)
+        p.tr.set_velocity(0, u0)
+        if combined:
+            p.tr.set_fields(1, u1, c)
+        else:
+            p.tr.set_velocity(1, u1)
+            p.tr.set_scalar(c)
+        out.append(p.gpu_step(wl.dt, 4))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    with pytest.raises(mmoc.MMOCError) as e:
+        p.tr.set_fields(2, u1, c)
+    assert e.value.status == -1
