@@ -226,10 +226,11 @@ mmoc_status mmoc_cfl_time_step(mmoc_ctx* ctx, double cfl, int level, double* tau
 /* Discrete H0 inner product with the P2 mass matrix M of the refined mesh
  * (the matrix of the H0 error norm and of the mass m(t) = 1^T M c, Sec. 3.1):
  * *out = (a - a_sub)^T M (b - b_sub).  All arrays are unique-layout
- * [n_unique] float64 device arrays; a = NULL stands for the vector of ones,
- * a_sub / b_sub = NULL for zero.  Exact for P2 functions on affine elements;
- * a blended mesh returns MMOC_E_UNSUPPORTED.  Deterministic (fixed summation
- * order); synchronises the stream. */
+ * [n_unique] float64 device arrays; a or b = NULL stands for the vector of
+ * ones, a_sub / b_sub = NULL for zero.  Exact for P2 functions on affine elements;
+ * on a blended mesh M is the assembled quadrature mass matrix of
+ * mmoc_fe_assemble (assembled at the first call).  Deterministic (fixed
+ * summation order); synchronises the stream. */
 mmoc_status mmoc_mass_inner(mmoc_ctx* ctx, const double* a_dev, const double* a_sub_dev, const double* b_dev,
                             const double* b_sub_dev, double* out);
 

@@ -68,6 +68,9 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
 inline int phys_level(const mmoc_ctx* c, int l) { return (c->rot + l) % c->lev_cap; }
 void mmoc_mlp_free_state(mmoc_ctx* c);
 void mmoc_fe_free_state(mmoc_ctx* c);
+// (a - a_sub)^T M (b - b_sub) with the assembled (quadrature) mass matrix
+mmoc_status mmoc_fe_mass_quadform(mmoc_ctx* c, const double* a, const double* a_sub, const double* b,
+                                  const double* b_sub, double* out);
 // lattice node (I, J, K), m >= I >= J >= K >= 0, in lexicographic order
 int64_t mmoc_lattice_index(int dim, int64_t I, int64_t J, int64_t K);
 

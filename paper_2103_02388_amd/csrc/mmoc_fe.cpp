@@ -363,6 +363,23 @@ void mmoc_fe_free_state(mmoc_ctx* c)
     c->fe = nullptr;
 }
 
+// (a - a_sub)^T M (b - b_sub) with the assembled mass matrix (the measures
+// of a blended mesh; arguments already checked by the caller)
+mmoc_status mmoc_fe_mass_quadform(mmoc_ctx* c, const double* a, const double* a_sub, const double* b,
+                                  const double* b_sub, double* out)
+{
+    mmoc_status st = ensure_fe(c);
+    if (st != MMOC_OK) return st;
+    fe_state* F = c->fe;
+    // the CG partial sums double as scratch: no solve runs concurrently on a context's stream
+    double* res = F->part_d + (size_t)fe::P_SLOTS * fe::kMaxRedBlocks - 1;
+    HIPCHK(c, fe::launch_quadform(csr_of(c), F->mv_d, a, a_sub, b, b_sub, F->part_d, res, c->stream),
+           "mass quadratic form");
+    HIPCHK(c, hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, c->stream), "mass quadratic form");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "mass quadratic form");
+    return MMOC_OK;
+}
+
 extern "C" {
 
 mmoc_status mmoc_fe_assemble(mmoc_ctx* c, int64_t* nnz)

@@ -389,6 +389,39 @@ __global__ __launch_bounds__(kB) void rhs_kernel(RhsArgs a)
     }
 }
 
+__global__ __launch_bounds__(kB) void quadform_kernel(Csr A, const double* __restrict__ v,
+                                                      const double* __restrict__ a, const double* __restrict__ a_sub,
+                                                      const double* __restrict__ b, const double* __restrict__ b_sub,
+                                                      double* __restrict__ part)
+{
+    __shared__ double buf[kLds];
+    double acc[1] = {0.0};
+    for (int64_t blk = blockIdx.x; blk < A.nrb; blk += gridDim.x) {
+        int i;
+        const double mb = stream_row_sum(
+            A, A.rb[blk], buf,
+            [&](int k) {
+                const int32_t j = A.ci[k];
+                const double bj = b ? b[j] : 1.0;
+                return v[k] * (b_sub ? bj - b_sub[j] : bj);
+            },
+            i);
+        if (i < 0) continue;
+        const double ai = (a ? a[i] : 1.0) - (a_sub ? a_sub[i] : 0.0);
+        acc[0] = fma(ai, mb, acc[0]);
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+__global__ __launch_bounds__(kB) void sum_kernel(const double* __restrict__ part, int G, double* __restrict__ out)
+{
+    const int slot[1] = {0};
+    double t[1];
+    sum_partials<1>(part, slot, G, t);
+    if (threadIdx.x == 0) *out = t[0];
+}
+
 // ------------------------------------------------------------------- CG
 //
 // Preconditioned CG in the Chronopoulos-Gear arrangement: the two inner
@@ -611,6 +644,15 @@ hipError_t launch_rhs(const RhsArgs& a, hipStream_t s)
 {
     if (a.A.nrb <= 0) return hipSuccess;
     rhs_kernel<<<(unsigned)a.A.nrb, kB, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_quadform(const Csr& A, const double* v, const double* a, const double* a_sub, const double* b,
+                           const double* b_sub, double* part, double* out, hipStream_t s)
+{
+    const int G = red_grid(A.nrb);
+    quadform_kernel<<<G, kB, 0, s>>>(A, v, a, a_sub, b, b_sub, part);
+    sum_kernel<<<1, kB, 0, s>>>(part, G, out);
     return hipGetLastError();
 }
 

@@ -82,6 +82,12 @@ struct RhsArgs {
 // right-hand side b (Dirichlet values lifted) and the initial iterate x
 hipError_t launch_rhs(const RhsArgs& a, hipStream_t s);
 
+// (a - a_sub)^T V (b - b_sub) for the CSR values V (a, b null: ones; a_sub,
+// b_sub null: zero): per-block partials into part[0..G), then their sum in
+// block order into *out
+hipError_t launch_quadform(const Csr& A, const double* v, const double* a, const double* a_sub, const double* b,
+                           const double* b_sub, double* part, double* out, hipStream_t s);
+
 // partial sums, part[slot * kMaxRedBlocks + block]: gamma = r.u by
 // iteration parity, delta = w.u, r.r, b.b
 enum { P_G0 = 0, P_G1 = 1, P_DE = 2, P_RR = 3, P_BB = 4, P_SLOTS = 5 };

@@ -99,7 +99,6 @@ mmoc_status mmoc_mass_inner(mmoc_ctx* c, const double* a, const double* a_sub, c
 {
     if (!c || !out) return MMOC_E_ARG;
     if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
-    if (c->blend) return fail(c, MMOC_E_UNSUPPORTED, "the mass matrix of a blended mesh is not affine per element");
     const size_t bytes = sizeof(double) * (size_t)c->N;
     const double* ptrs[4] = {a, a_sub, b, b_sub};
     const char* names[4] = {"a_dev", "a_sub_dev", "b_dev", "b_sub_dev"};
@@ -108,6 +107,8 @@ mmoc_status mmoc_mass_inner(mmoc_ctx* c, const double* a, const double* a_sub, c
         mmoc_status st = check_dev(c, ptrs[i], bytes, 8, names[i]);
         if (st != MMOC_OK) return st;
     }
+    // blended elements are not affine: the assembled quadrature mass matrix
+    if (c->blend) return mmoc_fe_mass_quadform(c, a, a_sub, b, b_sub, out);
     const int64_t nb = mmoc::mass_inner_blocks(c->dim, c->nm, c->n);
     mmoc_status st = ensure_reduction(c, std::max<int64_t>(nb, 2 * kRangeBlocks) + 2);
     if (st != MMOC_OK) return st;

@@ -8,6 +8,7 @@ within 5% for finite b and 1% for b = infinity, var within 2e-4).  The
 printed mass change dm is reported, not asserted: it is a small difference of
 large sums and the oracle does not reproduce it either."""
 import json
+import math
 import os
 
 import numpy as np
@@ -48,17 +49,24 @@ def test_mass_inner_closed_forms_and_oracle(wlf):
     assert tr.mass_inner(ga, ga2, gb, gb2) == got
 
 
-def test_field_range_and_blend_rejected():
+def test_field_range_and_blended_mass():
     wl, tr, om, xc = _pair(W.swirl3d, 3)
     rng = np.random.default_rng(22)
     v = rng.standard_normal(tr.N)
     v[5] = np.nan
     lo, hi = tr.field_range(torch.from_numpy(v).cuda())
     assert lo == np.nanmin(v) and hi == np.nanmax(v)
+    # blended meshes: the assembled quadrature mass matrix; the blended
+    # domains are the round shell and annulus, whose volume and area the
+    # quadrature reproduces
     sh = mmoc.Tracer.from_workload(W.shell3d(level=1), level=1)
-    with pytest.raises(mmoc.MMOCError) as e:
-        sh.mass_inner()
-    assert e.value.status == -6
+    vol = 4.0 / 3.0 * math.pi * (1.0 - 0.55 ** 3)
+    assert abs(sh.mass_inner() - vol) < 1e-5 * vol
+    an = mmoc.Tracer.from_workload(W.annulus2d(level=4))
+    assert abs(an.mass_inner() - 2.0 * math.pi) < 1e-12
+    xa = an.dof_coords()
+    r2 = (xa[0] ** 2 + xa[1] ** 2).contiguous()
+    assert abs(an.mass_inner(None, None, r2) - 2.5 * math.pi) < 1e-6
 
 
 def test_lookback_argument_errors():
