@@ -14,7 +14,10 @@ step's scalar.  All inputs (every velocity level of the run) are resident in
 device memory before timing starts.  value = particles per second of the
 float64 tracer (error <= 1e-12 against the CPU oracle); the float32-mixed
 tracer (<= 1e-5) and the surrogate step (network + RK4 check + fallback,
-<= 1e-4) are measured on the same run and reported beside it.
+<= 1e-4) are measured on the same run and reported beside it, as are the
+trace kernels alone on the large workloads (rising plumes, 1.7e7
+particles; the spherical shell, 1.7e8 particles, float32 paths) and the
+advection-diffusion run of Table 4 with its CG solve.
 
 The roofline entry is for the dominant kernel (the float64 trace): its
 algorithmic flops per particle (FMA = 2, see flops_per_particle) over its
@@ -99,6 +102,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--paths", default="fp64,fp32,fp32f", help="tracer paths to time (fp64 is the headline)")
     ap.add_argument("--no-diffusion", action="store_true")
+    ap.add_argument("--no-plume", action="store_true")
+    ap.add_argument("--no-shell", action="store_true", help="skip the 1.7e8-particle spherical shell")
     ap.add_argument("--diffusion-only", action="store_true",
                     help="only the advection-diffusion sub-result (for profiling its kernels)")
     ap.add_argument("--spmv-only", action="store_true",
@@ -187,6 +192,10 @@ def main():
                               "note": "float32 field records, float64 arithmetic"}
     if not args.no_surrogate:
         out["surrogate"] = time_surrogate(wl, S, min(args.steps, 50), min(args.warmup, 5), results)
+    if not args.no_plume:
+        out["plume3d"] = time_large(W.plume3d(), 120, ("fp64", "fp32", "fp32f"))
+    if not args.no_shell:
+        out["shell3d"] = time_large(W.shell3d(), 0, ("fp32", "fp32f"))
     if not args.no_diffusion:
         out["diffusion"] = time_diffusion()
     if not args.no_cpu_baseline:
@@ -315,6 +324,51 @@ def time_surrogate(wl, S, steps, warmup, results):
         out["speedup_vs_fp32_step"] = out["value"] / results["fp32"]["value"]
     if "fp32f" in results:
         out["speedup_vs_fp32_fields_step"] = out["value"] / results["fp32f"]["value"]
+    return out
+
+
+def time_large(wl, step, paths, reps=3):
+    """The trace kernel alone on a large workload (the rising plumes at 1.7e7
+    particles, or the 1.7e8-particle shell), per path: step `step` of the
+    run, RK4 with the workload's sub-steps, HIP events around each of `reps`
+    launches after one warm-up launch."""
+    import torch
+    from paper_2103_02388_amd import mmoc
+
+    prec = {"fp64": mmoc.MMOC_FP64, "fp32": mmoc.MMOC_FP32_MIXED, "fp32f": mmoc.MMOC_FP32_FIELDS}
+    names = {"fp64": "fp64", "fp32": "fp32_mixed", "fp32f": "fp32_fields"}
+    out = {"workload": wl.description, "level": wl.level}
+    for path in paths:
+        tr = mmoc.Tracer.from_workload(wl, precision=prec[path])
+        xt = tr.dof_coords().t().contiguous()
+        t_n = step * wl.dt
+        if wl.stationary:
+            tr.set_stationary(True)
+            tr.set_velocity(0, wl.velocity(xt, t_n).t().contiguous())
+        else:
+            tr.set_velocity(0, wl.velocity(xt, t_n).t().contiguous())
+            tr.set_velocity(1, wl.velocity(xt, t_n + wl.dt).t().contiguous())
+        tr.set_scalar(wl.scalar0(xt).contiguous())
+        del xt
+        chat = torch.empty(tr.N, dtype=tr.scalar_dtype, device="cuda")
+        X = torch.empty((wl.dim, tr.N), dtype=torch.float64, device="cuda")
+        mmoc.mmoc_trace_step(tr.ctx, wl.dt, wl.substeps, chat, X)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            mmoc.mmoc_trace_step(tr.ctx, wl.dt, wl.substeps, chat, X)
+            b.record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        out["particles"] = tr.N
+        out[names[path]] = {"kernel_ms": ms, "trace_only_particles_per_s": tr.N / (ms * 1e-3)}
+        tr.close()
+        del chat, X
+        torch.cuda.empty_cache()
+    if "fp64" in out:
+        for k in ("fp32_mixed", "fp32_fields"):
+            if k in out:
+                out[k]["speedup_vs_fp64"] = out["fp64"]["kernel_ms"] / out[k]["kernel_ms"]
     return out
 
 
