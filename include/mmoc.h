@@ -387,7 +387,7 @@ typedef struct {
  * definite), starting from c_hat.  With `dirichlet` given, the boundary DoFs
  * take those values, their rows become identity rows and their known values
  * move to the right-hand side of the other rows.  c_hat and c_out: device
- * float64 [N], distinct.  The call synchronises the stream once per batch
+ * float64 [N]; c_out must not alias any input.  The call synchronises the stream once per batch
  * of iterations to read the convergence state; not converging within
  * max_iter is reported in *info (optional), not as an error.
  * Errors: MMOC_E_ARG for theta outside [0, 1], tau <= 0, kappa < 0,

@@ -457,7 +457,8 @@ mmoc_status mmoc_diffusion_step(mmoc_ctx* c, const mmoc_diffusion_args* args, co
     const size_t bytes = sizeof(double) * (size_t)c->N;
     if ((st = check_dev(c, c_hat, bytes, 8, "c_hat")) != MMOC_OK) return st;
     if ((st = check_dev(c, c_out, bytes, 8, "c_out")) != MMOC_OK) return st;
-    if (c_hat == c_out) return fail(c, MMOC_E_ARG, "c_hat and c_out must not alias");
+    if (c_hat == c_out || A.q0 == c_out || A.q1 == c_out || A.dirichlet == c_out)
+        return fail(c, MMOC_E_ARG, "c_out must not alias c_hat, q0, q1 or dirichlet");
     if (A.q0 && (st = check_dev(c, A.q0, bytes, 8, "q0")) != MMOC_OK) return st;
     if (A.q1 && (st = check_dev(c, A.q1, bytes, 8, "q1")) != MMOC_OK) return st;
     if (A.dirichlet && (st = check_dev(c, A.dirichlet, bytes, 8, "dirichlet")) != MMOC_OK) return st;

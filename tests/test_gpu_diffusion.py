@@ -139,6 +139,10 @@ def test_diffusion_properties_and_errors():
         assert e.value.status == -1, kw
     with pytest.raises(mmoc.MMOCError):
         mmoc.mmoc_diffusion_step(p.tr.ctx, c, c, 1.0, 0.1, 0.1)
+    for kw in (dict(dirichlet=out), dict(q0=out), dict(q1=out)):
+        with pytest.raises(mmoc.MMOCError) as e:
+            mmoc.mmoc_diffusion_step(p.tr.ctx, c, out, 1.0, 0.1, 0.1, **kw)
+        assert e.value.status == -1
     # an iteration limit that is too small is reported, not raised
     out, info = p.tr.diffusion_step(c, 10.0, 1.0, max_iter=3, precond=0)
     torch.cuda.synchronize()
