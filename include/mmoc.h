@@ -31,7 +31,8 @@
  *  - A context is not thread-safe; use one context per host thread.
  *  - Unique DoF order ("unique layout"): macro-major, each DoF at its first
  *    occurrence; inside a macro, lattice nodes (I, J, K), m >= I >= J >= K
- *    >= 0, m = 2^(level+1), in lexicographic order.  A DoF on an interface
+ *    >= 0, in lexicographic order, with m = 2^(level+1) for P2 and m =
+ *    2^level for P1 (options.order).  A DoF on an interface
  *    belongs to the lowest-index macro that contains it (the paper leaves the
  *    choice open, Sec. 2.3.1 step (i)).  mmoc_dof_coords returns positions in
  *    this order.
