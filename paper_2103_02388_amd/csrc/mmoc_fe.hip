@@ -60,16 +60,25 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
     __syncthreads();
 }
 
-// totals of partial-sum slots written by the previous kernel (G blocks)
+// this thread's share of the partial-sum slots written by the previous
+// kernel (G blocks), in block order
 template <int NV>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, const int (&slot)[NV], int G,
-                                             double (&out)[NV])
+__device__ __forceinline__ void partial_loads(const double* __restrict__ part, const int (&slot)[NV], int G,
+                                              double (&out)[NV])
 {
 #pragma unroll
     for (int k = 0; k < NV; ++k) out[k] = 0.0;
     for (int b = threadIdx.x; b < G; b += kB)
 #pragma unroll
         for (int k = 0; k < NV; ++k) out[k] += part[slot[k] * kMaxRedBlocks + b];
+}
+
+// totals of partial-sum slots written by the previous kernel (G blocks)
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, const int (&slot)[NV], int G,
+                                             double (&out)[NV])
+{
+    partial_loads<NV>(part, slot, G, out);
     block_sum<NV>(out);
 }
 
@@ -483,11 +492,18 @@ __global__ __launch_bounds__(kB) void cg_spmv_kernel(CgArgs a, int par)
     double v[3] = {0.0, 0.0, 0.0};
     for (int64_t blk = blockIdx.x; blk < a.A.nrb; blk += gridDim.x) {
         if (blk != blockIdx.x) h = a.A.rb[blk];
+        // this thread's row values for the inner products, loaded while the
+        // row block streams
+        const int ir = h.x + (int)threadIdx.x;
+        double r = 0.0, u = 0.0;
+        if (ir < h.y) {
+            r = a.r[ir];
+            u = a.u[ir];
+        }
         int i;
         const double w = stream_row_sum(a.A, h, buf, [&](int k) { return a.ev[k] * a.u[a.A.ci[k]]; }, i);
         if (i < 0) continue;
         a.w[i] = w;
-        const double r = a.r[i], u = a.u[i];
         v[0] = fma(r, u, v[0]);
         v[1] = fma(w, u, v[1]);
         v[2] = fma(r, r, v[2]);
@@ -537,14 +553,15 @@ __global__ __launch_bounds__(kB) void cg_update_kernel(CgArgs a, int k)
     // that the two latencies overlap
     const int done = a.sc->done;
     const int4 h = a.A.rb[blockIdx.x];
+    const int par = k & 1;
+    const int slot[4] = {P_G0 + par, P_DE, P_RR, P_G0 + (par ^ 1)};
+    double t[4];
+    partial_loads<4>(a.part, slot, gridDim.x, t);
     const int i0 = h.x + (int)threadIdx.x;
     RowVals v0{};
     if (i0 < h.y) load_row(a, i0, v0);
     if (done) return;
-    const int par = k & 1;
-    const int slot[4] = {P_G0 + par, P_DE, P_RR, P_G0 + (par ^ 1)};
-    double t[4];
-    sum_partials<4>(a.part, slot, gridDim.x, t);
+    block_sum<4>(t);
     const double gamma = t[0], delta = t[1], rr = t[2];
     CgScalars* sc = a.sc;
     if (rr <= sc->thresh) {  // r_k is small enough: x_k is the result
