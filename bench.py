@@ -121,8 +121,8 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 10}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (particles are independent; "
-              "the sharding plan is in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (particles are independent "
+              "and would be sharded by macro ownership). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
