@@ -242,6 +242,13 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
     if (nm >= (1 << 27)) return fail(c, MMOC_E_ARG, "too many macros");
     const int64_t npm = lattice_count(d, c->m);
     if ((int64_t)nm * npm >= (int64_t)INT32_MAX) return fail(c, MMOC_E_ARG, "mesh too large for 32-bit slot indices");
+    {
+        // the gathers address records with 32-bit byte offsets
+        const bool f32 = c->prec != MMOC_FP64;
+        const uint64_t rec = (d == 3 && f32) ? 12 : (f32 ? 8 : 16);
+        if ((uint64_t)nm * (uint64_t)npm * rec >= (1ull << 32))
+            return fail(c, MMOC_E_ARG, "mesh too large: field arrays must stay below 4 GiB for 32-bit slot offsets");
+    }
     for (int i = 0; i < nv * d; ++i)
         if (!std::isfinite(vert[i])) return fail(c, MMOC_E_MESH, "vertex coordinate %d is not finite", i);
     for (int M = 0; M < nm; ++M)
@@ -457,9 +464,6 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
     if ((st = dev_alloc(c, &c->slot_uid_d, (size_t)c->nslots, "slot map")) != MMOC_OK) return st;
     const bool f32 = c->prec != MMOC_FP64;
     const size_t elem = f32 ? sizeof(float) : sizeof(double);
-    const int na = (d == 3 && f32) ? 3 : 2;  // components in the va records
-    if ((uint64_t)c->nslots * na * elem >= (1ull << 32))
-        return fail(c, MMOC_E_ARG, "mesh too large: field arrays must stay below 4 GiB for 32-bit slot offsets");
     if ((st = alloc_velocity_levels(c, c->lev_cap)) != MMOC_OK) return st;
     if ((st = alloc_clear(c, &c->cs_d, (size_t)c->nslots * elem, "scalar array")) != MMOC_OK) return st;
     HIPCHK(c, hipMemcpyAsync(c->geo_d, geo.data(), sizeof(MacroGeo) * nm, hipMemcpyHostToDevice, c->stream), "upload geometry");

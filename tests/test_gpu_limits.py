@@ -86,3 +86,22 @@ def test_offsets_past_2gib_single_tet_level9(prec):
     else:
         assert ex <= 1e-6
         assert ec <= (1e-6 * 10.0 + 1e-6) / max(np.abs(chr_).max(), 1e-300)
+
+
+@pytest.mark.parametrize("prec,level,ok", [(mmoc.MMOC_FP64, 9, False), (mmoc.MMOC_FP32_FIELDS, 9, False),
+                                           (mmoc.MMOC_FP64, 8, True)])
+def test_meshes_past_4gib_are_rejected_before_any_work(prec, level, ok):
+    """The six-tetrahedron cube at level 9 has 1.08e9 block slots: 17 GB of
+    float64 (u_x, u_y) records, 13 GB of float32 triples.  The upload is
+    refused with MMOC_E_ARG before any table is built; level 8 (135 million
+    slots, 2.2 GB) is accepted."""
+    wl = W.swirl3d(level=level)
+    print("limits: cube, level %d, precision %d" % (level, prec), flush=True)
+    if ok:
+        tr = mmoc.Tracer.from_workload(wl, precision=prec, level=level)
+        assert tr.N == 513 ** 3
+        tr.close()
+        return
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.Tracer.from_workload(wl, precision=prec, level=level)
+    assert e.value.status == -1 and "4 GiB" in str(e.value)  # MMOC_E_ARG
