@@ -170,6 +170,8 @@ def main():
                      "kernel": "trace_fp64_kernel<3,2,0>", "kernel_ms": r["kernel_ms"], "flop_per_particle": fpp,
                      "hbm_GBps_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / 1e9,
                      "hbm_frac_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / PEAK_HBM,
+                     "hbm_GBps_measured": (traffic_entry() / (r["kernel_ms"] * 1e-3) / 1e9
+                                           if traffic_entry() is not None else None),
                      "l1_tag_lookups_per_cu_cycle": (counter_summary() or {}).get("l1_tag_lookups_per_cu_cycle")},
         "trace_only_particles_per_s": N / (r["kernel_ms"] * 1e-3),
         "stats": r["stats"],
