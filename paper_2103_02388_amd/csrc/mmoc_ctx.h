@@ -34,6 +34,10 @@ struct mmoc_ctx {
     void* va_all = nullptr;  // (u_x,u_y) pairs, or (u_x,u_y,u_z) triples (3D float32)
     void* vb_all = nullptr;  // u_z (3D float64)
     int64_t va_lstride = 0, vb_lstride = 0;
+    // vb_all elements per slot: 2 for a two-level float64 3D ring, whose u_z
+    // values are paired per slot (ring slot 0, ring slot 1; vb_lstride = 1),
+    // so that a gather loads both levels' u_z at once; otherwise 1
+    int zs = 1;
     int lev_cap = 2;
     int rot = 0;
     void* cs_d = nullptr;                // scalar

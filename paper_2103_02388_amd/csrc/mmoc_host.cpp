@@ -115,13 +115,14 @@ mmoc_status alloc_velocity_levels(mmoc_ctx* c, int levels)
     const bool f32 = c->prec != MMOC_FP64;
     const size_t elem = f32 ? sizeof(float) : sizeof(double);
     const int na = (c->dim == 3 && f32) ? 3 : 2;
+    const bool split = c->dim == 3 && !f32;  // u_z in vb_all
     c->va_lstride = c->nslots * na;
-    c->vb_lstride = (c->dim == 3 && !f32) ? c->nslots : 0;
+    c->zs = (split && levels == 2) ? 2 : 1;
+    c->vb_lstride = split ? (c->zs == 2 ? 1 : c->nslots) : 0;
     mmoc_status st;
     if ((st = alloc_clear(c, &c->va_all, (size_t)c->va_lstride * elem * levels, "velocity arrays")) != MMOC_OK)
         return st;
-    if (c->vb_lstride &&
-        (st = alloc_clear(c, &c->vb_all, (size_t)c->vb_lstride * elem * levels, "velocity arrays")) != MMOC_OK)
+    if (split && (st = alloc_clear(c, &c->vb_all, (size_t)c->nslots * elem * levels, "velocity arrays")) != MMOC_OK)
         return st;
     c->lev_cap = levels;
     c->rot = 0;
@@ -508,7 +509,7 @@ static void velocity_dst(mmoc_ctx* c, int level, const double* u, mmoc::ScatterD
         d.dst[first] = d.dst[first + 1] = va;
         d.dst[first + 2] = vb;
         d.stride[first] = d.stride[first + 1] = 2;
-        d.stride[first + 2] = 1;
+        d.stride[first + 2] = c->zs;
         d.off[first] = 0;
         d.off[first + 1] = 1;
         d.off[first + 2] = 0;
@@ -634,6 +635,7 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.rk = c->rk;
         a.lsa = c->va_lstride;
         a.lsb = c->vb_lstride;
+        a.zs = c->zs;
         a.lev_cap = c->lev_cap;
         a.rot = c->rot;
         a.first = first;

@@ -90,6 +90,8 @@ struct TraceArgs {
     const T* vb;
     const T* cs;
     int64_t lsa, lsb;        // elements per velocity level in va / vb
+    int zs;                  // vb elements per slot: 1, or 2 when the u_z of a two-level
+                             // float64 ring are paired per slot (ring slot 0 first; lsb = 1)
     int lev_cap, rot;        // ring size and physical slot of logical level 0
     int first, n_int;        // trace from logical level first + n_int back to first
     int64_t n;               // particles traced by this launch (lanes)
@@ -155,9 +157,9 @@ hipError_t launch_mass_inner(int dim, int ord, const MacroGeo* geo, const int32_
 // out[0] = min c, out[1] = max c (NaNs skipped); partial holds 2 nblocks doubles
 hipError_t launch_range(const double* c, int64_t n, double* partial, int64_t nblocks, double* out, hipStream_t s);
 // out[0] = largest nodal speed of one velocity level in block slots (va
-// records of `stride` components, the last component in vb when vb is set);
-// partial holds nblocks doubles
-hipError_t launch_speed_max(const void* va, const void* vb, int fp32, int dim, int stride, int64_t nslots,
+// records of `stride` components, the last component in vb, zs elements per
+// slot, when vb is set); partial holds nblocks doubles
+hipError_t launch_speed_max(const void* va, const void* vb, int zs, int fp32, int dim, int stride, int64_t nslots,
                             double* partial, int64_t nblocks, double* out, hipStream_t s);
 
 }  // namespace mmoc

@@ -236,7 +236,7 @@ mmoc_status mmoc_cfl_time_step(mmoc_ctx* c, double cfl, int level, double* tau, 
     const void* vb = split ? static_cast<const char*>(c->vb_all) + (size_t)L * c->vb_lstride * elem : nullptr;
     double* res = c->red_d + c->red_cap - 2;
     HIPCHK(c,
-           mmoc::launch_speed_max(va, vb, c->prec != MMOC_FP64, c->dim, stride, c->nslots, c->red_d, kRangeBlocks,
+           mmoc::launch_speed_max(va, vb, c->zs, c->prec != MMOC_FP64, c->dim, stride, c->nslots, c->red_d, kRangeBlocks,
                                   res, c->stream),
            "largest speed");
     double u = 0.0;

@@ -208,11 +208,12 @@ __global__ __launch_bounds__(64) void range_final_kernel(const double* __restric
 }
 
 // per-block largest nodal speed |u| of one velocity level stored in block
-// slots: (x, y) pairs in va (stride 2) with z in vb, or (x, y, z) triples
-// in va (stride 3) with vb null
+// slots: (x, y) pairs in va (stride 2) with z in vb (zs elements per slot),
+// or (x, y, z) triples in va (stride 3) with vb null
 template <typename T>
-__global__ __launch_bounds__(kMB) void speed_max_kernel(const T* __restrict__ va, const T* __restrict__ vb, int dim,
-                                                        int stride, int64_t nslots, double* __restrict__ pmax)
+__global__ __launch_bounds__(kMB) void speed_max_kernel(const T* __restrict__ va, const T* __restrict__ vb, int zs,
+                                                        int dim, int stride, int64_t nslots,
+                                                        double* __restrict__ pmax)
 {
     __shared__ double sh[kMB / 64];
     double hi = 0.0;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kMB) void speed_max_kernel(const T* __restrict__ va
             s2 += v * v;
         }
         if (vb) {
-            const double v = (double)vb[q];
+            const double v = (double)vb[q * zs];
             s2 += v * v;
         }
         hi = fmax(hi, s2);
@@ -250,15 +251,15 @@ __global__ __launch_bounds__(64) void max_final_kernel(const double* __restrict_
 
 }  // namespace
 
-hipError_t launch_speed_max(const void* va, const void* vb, int fp32, int dim, int stride, int64_t nslots,
+hipError_t launch_speed_max(const void* va, const void* vb, int zs, int fp32, int dim, int stride, int64_t nslots,
                             double* partial, int64_t nblocks, double* out, hipStream_t s)
 {
     if (fp32)
-        speed_max_kernel<float><<<(unsigned)nblocks, kMB, 0, s>>>((const float*)va, (const float*)vb, dim, stride,
-                                                                  nslots, partial);
+        speed_max_kernel<float><<<(unsigned)nblocks, kMB, 0, s>>>((const float*)va, (const float*)vb, zs, dim,
+                                                                  stride, nslots, partial);
     else
-        speed_max_kernel<double><<<(unsigned)nblocks, kMB, 0, s>>>((const double*)va, (const double*)vb, dim, stride,
-                                                                   nslots, partial);
+        speed_max_kernel<double><<<(unsigned)nblocks, kMB, 0, s>>>((const double*)va, (const double*)vb, zs, dim,
+                                                                   stride, nslots, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     max_final_kernel<<<1, 64, 0, s>>>(partial, nblocks, out);

@@ -456,6 +456,8 @@ struct Levels {
     const T* eb;
     const T* la;  // later level
     const T* lb;
+    uint32_t zb;  // bytes per slot in the vb records
+    bool efirst;  // paired u_z records (two-level float64 ring): the earlier level is ring slot 0
 };
 
 template <int NLEV, typename T, typename R>
@@ -466,6 +468,7 @@ __device__ __forceinline__ Levels<T> levels_at(const TraceArgs<T>& A, double pos
         const int p = (A.rot + A.first) % A.lev_cap;
         L.ea = L.la = A.va + (int64_t)p * A.lsa;
         L.eb = L.lb = A.vb + (int64_t)p * A.lsb;
+        L.efirst = true;
         theta = R(1);
     } else {
         int iv = (int)pos;
@@ -477,19 +480,21 @@ __device__ __forceinline__ Levels<T> levels_at(const TraceArgs<T>& A, double pos
         L.lb = A.vb + (int64_t)late * A.lsb;
         L.ea = A.va + (int64_t)early * A.lsa;
         L.eb = A.vb + (int64_t)early * A.lsb;
+        L.efirst = early == 0;
     }
+    L.zb = (uint32_t)((A.zs > 1 ? A.zs : 1) * sizeof(T));
     return L;
 }
 
-// velocity vector of one level (records va, vb) at slot q
+// velocity vector of one level (records va, vb; zb bytes per vb slot) at slot q
 template <int DIM, typename T>
-__device__ __forceinline__ void load_vec(const T* va, const T* vb, uint32_t q, T* u)
+__device__ __forceinline__ void load_vec(const T* va, const T* vb, uint32_t zb, uint32_t q, T* u)
 {
     if constexpr (sizeof(T) == 8) {
         const double2 xy = ldv<double2>(va, q * 16u);
         u[0] = xy.x;
         u[1] = xy.y;
-        if constexpr (DIM == 3) u[2] = ldv<double>(vb, q * 8u);
+        if constexpr (DIM == 3) u[2] = ldv<double>(vb, q * zb);
     } else if constexpr (DIM == 3) {
         const F3 v = ldv<F3>(va, q * 12u);
         u[0] = v.x;
@@ -502,11 +507,35 @@ __device__ __forceinline__ void load_vec(const T* va, const T* vb, uint32_t q, T
     }
 }
 
+// Both levels' velocity at slot q.  ZP: the u_z values of a two-level
+// float64 ring sit side by side per slot (vb = ring slot 0's u_z, ring slot
+// 1's next to it), so one 16-byte load brings both: three loads per node
+// instead of four.
+template <int DIM, int NLEV, typename T, bool ZP>
+__device__ __forceinline__ void load_levels(const Levels<T>& Lv, const T* vb, uint32_t q, T* a, T* b)
+{
+    if constexpr (ZP) {
+        static_assert(DIM == 3 && NLEV == 2 && sizeof(T) == 8, "paired u_z records: float64, 3D, two levels");
+        const double2 xe = ldv<double2>(Lv.ea, q * 16u);
+        const double2 xl = ldv<double2>(Lv.la, q * 16u);
+        const double2 zz = ldv<double2>(vb, q * 16u);
+        a[0] = xe.x;
+        a[1] = xe.y;
+        a[2] = Lv.efirst ? zz.x : zz.y;
+        b[0] = xl.x;
+        b[1] = xl.y;
+        b[2] = Lv.efirst ? zz.y : zz.x;
+    } else {
+        load_vec<DIM, T>(Lv.ea, Lv.eb, Lv.zb, q, a);
+        if constexpr (NLEV == 2) load_vec<DIM, T>(Lv.la, Lv.lb, Lv.zb, q, b);
+    }
+}
+
 // Velocity at a stage point: P2 sums of both levels weighted (1 - theta,
 // theta), or the single level of a stationary run.
-template <int DIM, int NLEV, typename T, typename R, int ORD>
-__device__ __forceinline__ void gather_vel(const Levels<T>& Lv, uint32_t mbase, const Stencil<DIM, R, ORD>& st,
-                                           R theta, R* k)
+template <int DIM, int NLEV, typename T, typename R, int ORD, bool ZP = false>
+__device__ __forceinline__ void gather_vel(const Levels<T>& Lv, const T* vb, uint32_t mbase,
+                                           const Stencil<DIM, R, ORD>& st, R theta, R* k)
 {
     constexpr int NN = Stencil<DIM, R, ORD>::NN;
     R ua[DIM], ub[DIM];
@@ -518,13 +547,11 @@ __device__ __forceinline__ void gather_vel(const Levels<T>& Lv, uint32_t mbase, 
 #pragma unroll
     for (int q = 0; q < NN; ++q) {
         const uint32_t slot = mbase + (uint32_t)st.idx[q];
-        T a[DIM];
-        load_vec<DIM, T>(Lv.ea, Lv.eb, slot, a);
+        T a[DIM], b[DIM];
+        load_levels<DIM, NLEV, T, ZP>(Lv, vb, slot, a, b);
 #pragma unroll
         for (int i = 0; i < DIM; ++i) ua[i] = fma(st.phi[q], (R)a[i], ua[i]);
         if constexpr (NLEV == 2) {
-            T b[DIM];
-            load_vec<DIM, T>(Lv.la, Lv.lb, slot, b);
 #pragma unroll
             for (int i = 0; i < DIM; ++i) ub[i] = fma(st.phi[q], (R)b[i], ub[i]);
         }
@@ -535,14 +562,12 @@ __device__ __forceinline__ void gather_vel(const Levels<T>& Lv, uint32_t mbase, 
 
 // velocity at a lattice node: the nodal values (P2 interpolation is the
 // identity there)
-template <int DIM, int NLEV, typename T, typename R>
-__device__ __forceinline__ void nodal_vel(const Levels<T>& Lv, uint32_t slot, R theta, R* k)
+template <int DIM, int NLEV, typename T, typename R, bool ZP = false>
+__device__ __forceinline__ void nodal_vel(const Levels<T>& Lv, const T* vb, uint32_t slot, R theta, R* k)
 {
-    T a[DIM];
-    load_vec<DIM, T>(Lv.ea, Lv.eb, slot, a);
+    T a[DIM], b[DIM];
+    load_levels<DIM, NLEV, T, ZP>(Lv, vb, slot, a, b);
     if constexpr (NLEV == 2) {
-        T b[DIM];
-        load_vec<DIM, T>(Lv.la, Lv.lb, slot, b);
 #pragma unroll
         for (int i = 0; i < DIM; ++i) k[i] = (R(1) - theta) * (R)a[i] + theta * (R)b[i];
     } else {
@@ -614,10 +639,11 @@ __device__ __forceinline__ void count_flags(unsigned long long* stats, bool acti
 
 // T is the storage type of the fields: double (MMOC_FP64) or float
 // (MMOC_FP32_FIELDS: float32 records, float64 arithmetic throughout).
+// ZP: the u_z records of a two-level float64 ring are paired per slot.
 // GENERIC: a general explicit Runge-Kutta method from A.rk (the paper uses
 // RK4 and notes that any explicit RK method applies, Sec. 3.1); otherwise the
 // classical RK4 with its weights folded into the code.
-template <int DIM, int NLEV, int BLEND, typename T, bool GENERIC, int ORD>
+template <int DIM, int NLEV, int BLEND, typename T, bool GENERIC, int ORD, bool ZP = false>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP64)))
 void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T* __restrict__ c_hat,
                        double* __restrict__ X, unsigned long long* __restrict__ stats)
@@ -655,7 +681,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                 lmin = lam_min<DIM, double>(l0, s);
             }
             micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
-            gather_vel<DIM, NLEV, T, double>(Lv, mbase, st, theta, k);
+            gather_vel<DIM, NLEV, T, double, ORD, ZP>(Lv, A.vb, mbase, st, theta, k);
         };
         const int nsub = A.substeps * A.n_int;
         if constexpr (GENERIC) {
@@ -677,7 +703,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                         double theta;
                         const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)j + A.rk.c[q]) * invS, theta);
                         if ((j == 0 && q == 0) || (home && same_point<DIM>(y, Y)))
-                            nodal_vel<DIM, NLEV, T, double>(Lv, own_slot, theta, K[q]);
+                            nodal_vel<DIM, NLEV, T, double, ZP>(Lv, A.vb, own_slot, theta, K[q]);
                         else
                             velocity(y, Lv, theta, K[q]);
                     }
@@ -708,7 +734,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                     const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)j + as) * invS, theta);
                     if ((j == 0 && stg == 0) || (home && same_point<DIM>(y, Y))) {
                         // the stage point is the particle's own DoF
-                        nodal_vel<DIM, NLEV, T, double>(Lv, own_slot, theta, ks);
+                        nodal_vel<DIM, NLEV, T, double, ZP>(Lv, A.vb, own_slot, theta, ks);
                     } else {
                         velocity(y, Lv, theta, ks);
                     }
@@ -959,10 +985,10 @@ void trace_fp32_kernel(const TraceArgs<float> A)
                 float theta;
                 const Levels<float> Lv = levels_at<NLEV, float, float>(A, ((double)j + as) * invSd, theta);
                 if ((j == 0 && stg == 0) || (home && same_point<DIM>(y, Y))) {
-                    nodal_vel<DIM, NLEV, float, float>(Lv, own_slot, theta, ks);
+                    nodal_vel<DIM, NLEV, float, float>(Lv, A.vb, own_slot, theta, ks);
                 } else {
                     locate32<DIM, BLEND, ORD>(A, M, mbase, y, st, flags);
-                    gather_vel<DIM, NLEV, float, float>(Lv, mbase, st, theta, ks);
+                    gather_vel<DIM, NLEV, float, float>(Lv, A.vb, mbase, st, theta, ks);
                 }
                 const float wst = (stg == 0 || stg == 3) ? 1.0f : 2.0f;
                 const float cnext = stg == 2 ? h : hh;
@@ -1217,6 +1243,15 @@ hipError_t launch_trace_f64g(int dim, int blend, const TraceArgs<T>& a0, hipStre
     a.xcd_log2 = xcd_log2_fp64(a.n);
     const dim3 grid(grid_xcd(a.n, a.xcd_log2)), block(kTB);
     const bool st = a.nlev == 1;
+    if constexpr (sizeof(T) == 8) {
+        // paired u_z records of a two-level ring (both levels in one load)
+        if (a.zs == 2 && dim == 3 && !st) {
+            if (!blend) trace_fp64_kernel<3, 2, 0, T, G, ORD, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+            else if (ORD == 2) trace_fp64_kernel<3, 2, 1, T, G, 2, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+            else return hipErrorNotSupported;
+            return hipGetLastError();
+        }
+    }
     if (dim == 2 && !blend) {
         if (st) trace_fp64_kernel<2, 1, 0, T, G, ORD><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
         else trace_fp64_kernel<2, 2, 0, T, G, ORD><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);

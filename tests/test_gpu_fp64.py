@@ -232,3 +232,36 @@ def test_set_fields_equals_separate_calls(prec):
     with pytest.raises(mmoc.MMOCError) as e:
         p.tr.set_fields(2, u1, c)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("swap", [False, True])
+def test_paired_uz_records_equal_unpaired(swap):
+    """A two-level float64 3D context pairs the two levels' u_z per slot (one
+    load brings both); a three-level context keeps one u_z array per level.
+    The same step through both must agree bit for bit, with the earlier level
+    in either ring slot (swap: after a level swap it sits in ring slot 1)."""
+    wl = W.swirl3d()
+    res = []
+    for levels in (2, 3):
+        tr = mmoc.Tracer.from_workload(wl, level=3)
+        if levels == 3:
+            tr.set_level_count(3)
+        xt = tr.dof_coords().t().contiguous()
+        u0 = wl.velocity(xt, 0.4).t().contiguous()
+        u1 = wl.velocity(xt, 0.4 + wl.dt).t().contiguous()
+        if swap:
+            tr.set_velocity(1, u0)
+            tr.swap_levels()  # the ring turns: logical level 0 now sits in ring slot 1
+            tr.set_velocity(1, u1)
+        else:
+            tr.set_velocity(0, u0)
+            tr.set_velocity(1, u1)
+        tr.set_scalar(wl.scalar0(xt).contiguous())
+        ch, X = tr.trace_span(0, 1, wl.dt, 4) if levels == 3 else tr.trace_step(wl.dt, 4)
+        tau, umax, _ = mmoc.mmoc_cfl_time_step(tr.ctx, 1.0, 1)
+        torch.cuda.synchronize()
+        res.append((ch.cpu().numpy(), X.cpu().numpy(), umax))
+        tr.close()
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[0][2] == res[1][2]
