@@ -510,7 +510,9 @@ __device__ __forceinline__ void load_vec(const T* va, const T* vb, uint32_t zb, 
 // Both levels' velocity at slot q.  ZP: the u_z values of a two-level
 // float64 ring sit side by side per slot (vb = ring slot 0's u_z, ring slot
 // 1's next to it), so one 16-byte load brings both: three loads per node
-// instead of four.
+// instead of four.  a[2] and b[2] are then ring slots 0 and 1, not the
+// earlier and later level; the callers swap the two z sums once when the
+// earlier level is ring slot 1 (Levels::efirst false).
 template <int DIM, int NLEV, typename T, bool ZP>
 __device__ __forceinline__ void load_levels(const Levels<T>& Lv, const T* vb, uint32_t q, T* a, T* b)
 {
@@ -521,10 +523,10 @@ __device__ __forceinline__ void load_levels(const Levels<T>& Lv, const T* vb, ui
         const double2 zz = ldv<double2>(vb, q * 16u);
         a[0] = xe.x;
         a[1] = xe.y;
-        a[2] = Lv.efirst ? zz.x : zz.y;
+        a[2] = zz.x;
         b[0] = xl.x;
         b[1] = xl.y;
-        b[2] = Lv.efirst ? zz.y : zz.x;
+        b[2] = zz.y;
     } else {
         load_vec<DIM, T>(Lv.ea, Lv.eb, Lv.zb, q, a);
         if constexpr (NLEV == 2) load_vec<DIM, T>(Lv.la, Lv.lb, Lv.zb, q, b);
@@ -556,6 +558,11 @@ __device__ __forceinline__ void gather_vel(const Levels<T>& Lv, const T* vb, uin
             for (int i = 0; i < DIM; ++i) ub[i] = fma(st.phi[q], (R)b[i], ub[i]);
         }
     }
+    if constexpr (ZP) {
+        const R z0 = ua[2], z1 = ub[2];
+        ua[2] = Lv.efirst ? z0 : z1;
+        ub[2] = Lv.efirst ? z1 : z0;
+    }
 #pragma unroll
     for (int i = 0; i < DIM; ++i) k[i] = NLEV == 2 ? (R(1) - theta) * ua[i] + theta * ub[i] : ua[i];
 }
@@ -567,6 +574,11 @@ __device__ __forceinline__ void nodal_vel(const Levels<T>& Lv, const T* vb, uint
 {
     T a[DIM], b[DIM];
     load_levels<DIM, NLEV, T, ZP>(Lv, vb, slot, a, b);
+    if constexpr (ZP) {
+        const T z0 = a[2], z1 = b[2];
+        a[2] = Lv.efirst ? z0 : z1;
+        b[2] = Lv.efirst ? z1 : z0;
+    }
     if constexpr (NLEV == 2) {
 #pragma unroll
         for (int i = 0; i < DIM; ++i) k[i] = (R(1) - theta) * (R)a[i] + theta * (R)b[i];
