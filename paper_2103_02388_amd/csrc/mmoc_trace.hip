@@ -157,11 +157,34 @@ struct Geo64 {
 // evaluation instead of being kept in registers across the loop.  When every
 // active lane of the wave is in the same macro (the common case) the record
 // is read through scalar loads into scalar registers; otherwise each lane
-// reads its own (an L1/L2 hit: the table is small).
+// reads its own, from the block's LDS copy when the mesh has few macros
+// (sgeo, see stage_geo), else from global memory (an L1/L2 hit: the table
+// is small).
 typedef __attribute__((address_space(4))) const MacroGeo* ConstGeo;
+typedef __attribute__((address_space(3))) const MacroGeo* LdsGeo;
+
+// macros whose geometry the float64 trace kernel copies into LDS (4 KB)
+constexpr int kLdsGeo = 16;
+
+// Copies the geometry of a mesh of at most kLdsGeo macros into the block's
+// LDS array and returns it (null for larger meshes).  Every thread of the
+// block must call it.
+__device__ __forceinline__ const MacroGeo* stage_geo(const MacroGeo* __restrict__ geo, int nm, MacroGeo* sgeo)
+{
+    const bool on = nm <= kLdsGeo;
+    if (on) {
+        const uint4* src = reinterpret_cast<const uint4*>(geo);
+        uint4* dst = reinterpret_cast<uint4*>(sgeo);
+        constexpr int kChunks = (int)(sizeof(MacroGeo) / sizeof(uint4));
+        for (int i = (int)threadIdx.x; i < nm * kChunks; i += (int)blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    return on ? sgeo : nullptr;
+}
 
 template <int DIM, int BLEND>
-__device__ __forceinline__ double ref_at(const MacroGeo* __restrict__ geo, int M, const double* y, double* s)
+__device__ __forceinline__ double ref_at(const MacroGeo* __restrict__ geo, int M, const double* y, double* s,
+                                         const MacroGeo* sgeo = nullptr)
 {
     const int M0 = __builtin_amdgcn_readfirstlane(M);
     Geo64<DIM, BLEND> G;
@@ -175,7 +198,8 @@ __device__ __forceinline__ double ref_at(const MacroGeo* __restrict__ geo, int M
         __asm__ volatile("");
         return l0;
     }
-    G.load(geo, M);
+    if (sgeo) G.load((LdsGeo)sgeo, M);
+    else G.load(geo, M);
     return G.ref(y, s);
 }
 
@@ -660,6 +684,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP
 void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T* __restrict__ c_hat,
                        double* __restrict__ X, unsigned long long* __restrict__ stats)
 {
+    __shared__ MacroGeo sgeo[kLdsGeo];
+    const MacroGeo* sg = stage_geo(geo, A.nm, sgeo);
     const int64_t t = logical_block(A.xcd_log2) * kTB + threadIdx.x;
     const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
     unsigned flags = 0;
@@ -681,7 +707,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
         // velocity at stage point y and stage time theta (Sec. 2.3.2: walk
         // from the previous macro, micro element, P2 sums of both levels)
         auto velocity = [&](const double* y, const Levels<T>& Lv, double theta, double* k) {
-            l0 = ref_at<DIM, BLEND>(geo, M, y, s);
+            l0 = ref_at<DIM, BLEND>(geo, M, y, s, sg);
             lmin = lam_min<DIM, double>(l0, s);
             if (lmin < -A.eps_in) {
                 const unsigned r = walk64<DIM, BLEND>(geo, A.nm, A.max_hops, A.eps_in, M, y[0], y[1],
@@ -689,7 +715,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                 flags |= r >> 27;
                 M = (int)(r & ((1u << 27) - 1));
                 mbase = (uint32_t)M * (uint32_t)A.npm;
-                l0 = ref_at<DIM, BLEND>(geo, M, y, s);
+                l0 = ref_at<DIM, BLEND>(geo, M, y, s, sg);
                 lmin = lam_min<DIM, double>(l0, s);
             }
             micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
@@ -772,7 +798,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
         if (home) {
             v = (double)ldv<T>(A.cs, own_slot * (uint32_t)sizeof(T));
         } else {
-            l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
+            l0 = ref_at<DIM, BLEND>(geo, M, Y, s, sg);
             lmin = lam_min<DIM, double>(l0, s);
             if (lmin < -A.eps_in) {
                 const unsigned r =
@@ -780,7 +806,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                 flags |= r >> 27;
                 M = (int)(r & ((1u << 27) - 1));
                 mbase = (uint32_t)M * (uint32_t)A.npm;
-                l0 = ref_at<DIM, BLEND>(geo, M, Y, s);
+                l0 = ref_at<DIM, BLEND>(geo, M, Y, s, sg);
                 lmin = lam_min<DIM, double>(l0, s);
             }
             micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
