@@ -883,7 +883,8 @@ struct Geo32 {
 // float32 reference coordinates of y in macro M (geometry read per
 // evaluation, through scalar loads when the wave is in one macro)
 template <int DIM, int BLEND>
-__device__ __forceinline__ float ref32_at(const MacroGeo* __restrict__ geo, int M, const double* y, float* s)
+__device__ __forceinline__ float ref32_at(const MacroGeo* __restrict__ geo, int M, const double* y, float* s,
+                                          const MacroGeo* sgeo = nullptr)
 {
     const int M0 = __builtin_amdgcn_readfirstlane(M);
     Geo32<DIM, BLEND> G;
@@ -893,7 +894,8 @@ __device__ __forceinline__ float ref32_at(const MacroGeo* __restrict__ geo, int 
         __asm__ volatile("");
         return l0;
     }
-    G.load(geo, M);
+    if (sgeo) G.load((LdsGeo)sgeo, M);
+    else G.load(geo, M);
     return G.ref(y, s);
 }
 
@@ -933,10 +935,10 @@ __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int 
 // and its element is selected from the clamped barycentrics as in float64.
 template <int DIM, int BLEND, int ORD>
 __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint32_t& mbase, const double* y,
-                                         Stencil<DIM, float, ORD>& st, unsigned& flags)
+                                         Stencil<DIM, float, ORD>& st, unsigned& flags, const MacroGeo* sg = nullptr)
 {
     float s[DIM];
-    const float l0 = ref32_at<DIM, BLEND>(A.geo, M, y, s);
+    const float l0 = ref32_at<DIM, BLEND>(A.geo, M, y, s, sg);
     const float lmin = lam_min<DIM, float>(l0, s);
     bool macro_redo = lmin < A.eps32_macro;
     if (macro_redo && lmin > -A.eps32_macro) {
@@ -956,7 +958,7 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint
         // a point on or next to an interior face -- the micro element follows
         // from them; otherwise the full float64 re-location below walks.
         double s64[DIM];
-        const double l064 = ref_at<DIM, BLEND>(A.geo, M, y, s64);
+        const double l064 = ref_at<DIM, BLEND>(A.geo, M, y, s64, sg);
         const double lmin64 = lam_min<DIM, double>(l064, s64);
         if (lmin64 >= -A.eps_in) {
             flags |= LF_TIEBAND;
@@ -992,6 +994,8 @@ template <int DIM, int NLEV, int BLEND, int ORD>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP32)))
 void trace_fp32_kernel(const TraceArgs<float> A)
 {
+    __shared__ MacroGeo sgeo[kLdsGeo];
+    const MacroGeo* sg = stage_geo(A.geo, A.nm, sgeo);
     const int64_t t = logical_block(A.xcd_log2) * kTB + threadIdx.x;
     const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
     unsigned flags = 0;
@@ -1025,7 +1029,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
                 if ((j == 0 && stg == 0) || (home && same_point<DIM>(y, Y))) {
                     nodal_vel<DIM, NLEV, float, float>(Lv, A.vb, own_slot, theta, ks);
                 } else {
-                    locate32<DIM, BLEND, ORD>(A, M, mbase, y, st, flags);
+                    locate32<DIM, BLEND, ORD>(A, M, mbase, y, st, flags, sg);
                     gather_vel<DIM, NLEV, float, float>(Lv, A.vb, mbase, st, theta, ks);
                 }
                 const float wst = (stg == 0 || stg == 3) ? 1.0f : 2.0f;
@@ -1048,7 +1052,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
         if (home) {
             v = ldv<float>(A.cs, own_slot * 4u);
         } else {
-            locate32<DIM, BLEND, ORD>(A, M, mbase, Y, st, flags);
+            locate32<DIM, BLEND, ORD>(A, M, mbase, Y, st, flags, sg);
             v = gather_scalar<DIM, float, float>(A, mbase, st);
         }
         bool bad = v != v;
