@@ -306,8 +306,8 @@ mmoc_status mmoc_mlp_set_weights(mmoc_ctx* ctx, const float* host_params, int64_
  * written to X_dev (SoA [dim][n_unique] float64). */
 mmoc_status mmoc_mlp_infer(mmoc_ctx* ctx, double t_np1, double dt, double* X_dev);
 
-/* Surrogate step: inference for all particles, then an RK4 re-trace (FP32
- * mixed tracer, same fields) of a seeded sample of about check_fraction of
+/* Surrogate step: inference for all particles, then an RK4 re-trace (the
+ * context's own tracer and precision, same fields) of a seeded sample of about check_fraction of
  * the particles (hash(seed, step, i) < check_fraction, with at least one per
  * tile of 128 particles); every checked particle keeps its RK4 result, and
  * every particle of a tile in which some checked residual

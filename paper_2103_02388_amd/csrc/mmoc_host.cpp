@@ -106,26 +106,42 @@ mmoc_status alloc_clear(mmoc_ctx* c, void** p, size_t bytes, const char* what)
 }
 
 // (Re)allocates the ring of `levels` velocity levels; every level unset.
+// The old ring is released first (the new one may need its memory).  The
+// context's ring fields change only once both new arrays exist; if either
+// allocation fails the context holds no levels (lev_cap 0, nothing set), so
+// that every later trace call fails with MMOC_E_STATE until the level count
+// is set again.
 mmoc_status alloc_velocity_levels(mmoc_ctx* c, int levels)
 {
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->va_all);
     (void)hipFree(c->vb_all);
     c->va_all = c->vb_all = nullptr;
+    c->lev_cap = 0;
+    c->rot = 0;
+    c->vel_set.assign(2, 0);
     const bool f32 = c->prec != MMOC_FP64;
     const size_t elem = f32 ? sizeof(float) : sizeof(double);
     const int na = (c->dim == 3 && f32) ? 3 : 2;
     const bool split = c->dim == 3 && !f32;  // u_z in vb_all
-    c->va_lstride = c->nslots * na;
-    c->zs = (split && levels == 2) ? 2 : 1;
-    c->vb_lstride = split ? (c->zs == 2 ? 1 : c->nslots) : 0;
+    const int64_t lsa = c->nslots * na;
+    const int zs = (split && levels == 2) ? 2 : 1;
+    const int64_t lsb = split ? (zs == 2 ? 1 : c->nslots) : 0;
+    void* va = nullptr;
+    void* vb = nullptr;
     mmoc_status st;
-    if ((st = alloc_clear(c, &c->va_all, (size_t)c->va_lstride * elem * levels, "velocity arrays")) != MMOC_OK)
+    if ((st = alloc_clear(c, &va, (size_t)lsa * elem * levels, "velocity arrays")) != MMOC_OK) return st;
+    if (split && (st = alloc_clear(c, &vb, (size_t)c->nslots * elem * levels, "velocity arrays")) != MMOC_OK) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(va);
         return st;
-    if (split && (st = alloc_clear(c, &c->vb_all, (size_t)c->nslots * elem * levels, "velocity arrays")) != MMOC_OK)
-        return st;
+    }
+    c->va_all = va;
+    c->vb_all = vb;
+    c->va_lstride = lsa;
+    c->vb_lstride = lsb;
+    c->zs = zs;
     c->lev_cap = levels;
-    c->rot = 0;
     c->vel_set.assign(levels, 0);
     return MMOC_OK;
 }

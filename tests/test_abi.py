@@ -134,3 +134,36 @@ def test_mesh_errors():
     with pytest.raises(mmoc.MMOCError) as e:
         mmoc.Tracer(2, 1, va, ma, blend=1, options=opt)
     assert e.value.status == -6
+
+
+@pytest.mark.gpu
+def test_failed_level_ring_leaves_no_levels():
+    """A velocity ring that cannot be allocated (65536 levels of a level-6
+    cube: about 2.3 TB) fails with MMOC_E_NOMEM and leaves the context with
+    no levels: traces and level uploads are refused until the level count is
+    set again, after which the context works as before."""
+    import torch
+    from paper_2103_02388_amd import mmoc
+    wl = W.swirl3d(level=6)
+    tr = mmoc.Tracer.from_workload(wl)
+    N = tr.N
+    c = torch.zeros(N, dtype=torch.float64, device=tr.device)
+    u = torch.zeros((3, N), dtype=torch.float64, device=tr.device)
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.mmoc_set_level_count(tr.ctx, 65536)
+    assert e.value.status == -5
+    tr.set_scalar(c)
+    with pytest.raises(mmoc.MMOCError) as e:
+        tr.trace_step(0.01, 1)
+    assert e.value.status == -3
+    with pytest.raises(mmoc.MMOCError) as e:
+        mmoc.mmoc_set_velocity(tr.ctx, 0, u)
+    assert e.value.status == -1
+    mmoc.mmoc_set_level_count(tr.ctx, 2)
+    tr.set_velocity(0, u)
+    tr.set_velocity(1, u)
+    ch, X = tr.trace_step(0.01, 1)
+    torch.cuda.synchronize()
+    x = tr.dof_coords()
+    assert torch.equal(X, x)  # zero velocity: every particle stays at its DoF
+    tr.close()
