@@ -1,29 +1,37 @@
 #!/usr/bin/env python3
 """Throughput of the MMOC particle tracer on one MI355X.
 
-Workload: the 3D swirl -- unit cube of 6 Kuhn macro tetrahedra refined to
-level 5, 65^3 = 274625 P2 DoFs = particles, LeVeque's deformation field with
-g(t) = cos(pi t / 1.5) sampled at every time level, two Gaussian blobs as the
-scalar, dt = T/20 (CFL ~ 5), 4 RK4 sub-steps, a 50-step run.
+Headline workload: the thick spherical shell r in [0.55, 1] -- an
+icosahedral macro mesh of 3840 tetrahedra with radial blending, refined to
+level 5, 168,428,034 P2 DoFs = particles; a stationary velocity from 16
+seeded toroidal/poloidal spherical-harmonic modes (no normal flow at either
+radius), the scalar a step at r = 0.8 plus 1% nodal noise, dt = 5 h_min /
+max|u| (CFL 5 on the radial micro edge), 4 RK4 sub-steps; the largest
+configuration that fits one GPU.  The tracer runs in float64, the paper's
+precision (error <= 1e-12 against the CPU oracle).
 
-One timed step is one full MMOC advection step of the time loop: the new
-velocity level and the current scalar are copied into the library's block
-layout (field ingestion), then every particle is created, traced back with
-RK4 and the scalar evaluated at its departure point; the result is the next
-step's scalar.  All inputs (every velocity level of the run) are resident in
-device memory before timing starts.  value = particles per second of the
-float64 tracer (error <= 1e-12 against the CPU oracle); the float32-mixed
-tracer (<= 1e-5) and the surrogate step (network + RK4 check + fallback,
-<= 1e-4) are measured on the same run and reported beside it, as are the
-trace kernels alone on the large workloads (rising plumes, 1.7e7
-particles; the spherical shell, 1.7e8 particles, float32 paths) and the
-advection-diffusion run of Table 4 with its CG solve.
+One timed step is one full MMOC advection step of the time loop: the
+current scalar is copied into the library's block layout (field
+ingestion), then every particle is created, traced back with RK4 through
+the stationary velocity and the scalar evaluated at its departure point;
+the result is the next step's scalar.  The velocity and the initial scalar
+are resident in device memory before timing starts.  value = particles per
+second of the float64 tracer.  Beside it, on the same shell: the
+float32-mixed tracer (float32 stages, location and interpolation, float64
+tie-break at macro faces, <= 1e-5) and the float32-fields tracer (float32
+records, float64 arithmetic), and the measured error of the first step
+against the oracle on a seeded subset of 1e6 particles.  Sub-results: the
+3D swirl (274,625 particles, time-dependent velocity, all three tracers),
+the trace kernels on the rising plumes (1.7e7 particles), the surrogate
+step and the advection-diffusion run of Table 4 with its CG solve.
 
-The roofline entry is for the dominant kernel (the float64 trace): its
-algorithmic flops per particle (FMA = 2, see flops_per_particle) over its
-mean duration from HIP events recorded around each launch on the stream it
-runs on.  cpu_baseline times the CPU oracle (single-threaded float64 C) on a
-bounded sample of the same workload.
+The roofline entry is for the dominant kernel (the float64 trace on the
+shell): its algorithmic flops per particle (FMA = 2, see
+flops_per_particle) over its mean duration from HIP events recorded around
+each launch on the stream it runs on.  cpu_baseline times the CPU oracle
+(float64 C, unchanged) on the seeded 1e6-particle subset of the same step,
+on all host cores (one thread per core, disjoint particle ranges) and on
+one core.
 """
 from __future__ import annotations
 
@@ -40,21 +48,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 TRACE_SRC = os.path.join(ROOT, "paper_2103_02388_amd", "csrc", "mmoc_trace.hip")
-TRAFFIC = os.path.join(ROOT, "profiles", "trace_fp64_swirl3d_traffic.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "trace_fp64_shell3d_traffic.json")
+SUBSET = 1_000_000  # particles of the oracle's share of the shell step
 
 
-def flops_per_particle(dim, nlev, S):
+def flops_per_particle(dim, nlev, S, blend=False):
     """Algorithmic flops of one particle's step (FMA = 2).  Per stage
     evaluation: reference coordinates (offset dim, matrix 2 dim^2, lambda_0
-    dim + 1), micro location and P2 basis (Kuhn sums 2(dim - 1), scaling 2 dim,
-    fractional parts 2 dim, micro barycentrics dim + 1, vertex shape functions
-    3 (dim + 1), edge shape functions 2 per edge), the P2 sums (2 per node,
-    component and level), the time interpolation (3 dim) and the stage update
-    (4 dim); 2 dim per sub-step for the departure point; the scalar evaluation
-    at the end.  The first stage evaluation (at the particle's own DoF) is
-    counted as a full one."""
+    dim + 1), with blending the inverse map Phi^-1(y) = y c |y| / (n.y) first
+    (two dot products 4 dim - 2, a square root, a product and a quotient, and
+    dim fused scalings: 6 dim + 1), micro location and P2 basis (Kuhn sums
+    2(dim - 1), scaling 2 dim, fractional parts 2 dim, micro barycentrics
+    dim + 1, vertex shape functions 3 (dim + 1), edge shape functions 2 per
+    edge), the P2 sums (2 per node, component and level), the time
+    interpolation (3 dim, two levels only) and the stage update (4 dim);
+    2 dim per sub-step for the departure point; the scalar evaluation at the
+    end.  The first stage evaluation (at the particle's own DoF) is counted
+    as a full one; particle creation is not counted."""
     nn = (dim + 1) * (dim + 2) // 2
-    ref = dim + 2 * dim * dim + dim + 1
+    ref = dim + 2 * dim * dim + dim + 1 + ((6 * dim + 1) if blend else 0)
     micro = (2 * (dim - 1) + 2 * dim + 2 * dim) + (dim + 1) + 3 * (dim + 1) + 2 * (nn - dim - 1)
     gather = 2 * nn * dim * nlev + (3 * dim if nlev == 2 else 0)
     stage = 4 * dim
@@ -75,8 +87,8 @@ PEAK_HBM = 8.0e12
 
 
 def counter_summary():
-    """The committed rocprofv3 counter summary of the float64 trace kernel,
-    if it was taken on the current kernel source (else None)."""
+    """The committed rocprofv3 counter summary of the float64 trace kernel on
+    the shell, if it was taken on the current kernel source (else None)."""
     try:
         d = json.load(open(TRAFFIC))
         sha = hashlib.sha256(open(TRACE_SRC, "rb").read()).hexdigest()
@@ -86,24 +98,54 @@ def counter_summary():
 
 
 def traffic_entry():
-    """HBM bytes per launch of the float64 trace kernel (FETCH_SIZE +
-    WRITE_SIZE, scaled by a plain copy's counts)."""
+    """HBM bytes per launch of the float64 trace kernel on the shell
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counts)."""
     d = counter_summary()
     return d["hbm_bytes_per_launch"] if d else None
+
+
+ELEM_CACHE = 1
+
+
+def options(path="fp64"):
+    from paper_2103_02388_amd import mmoc
+    o = mmoc.mmoc_default_options()
+    o.elem_cache = ELEM_CACHE
+    if path == "fp32b":
+        o.eps32_micro = MICRO_BAND
+    return o
+
+
+def log(msg):
+    """progress line on stderr (the JSON result is the only stdout line)"""
+    print("[bench %.1fs] %s" % (time.perf_counter() - T0, msg), file=sys.stderr, flush=True)
+
+
+T0 = time.perf_counter()
+PREC = {"fp64": "MMOC_FP64", "fp32": "MMOC_FP32_MIXED", "fp32f": "MMOC_FP32_FIELDS", "fp32b": "MMOC_FP32_MIXED"}
+NAMES = {"fp64": "fp64", "fp32": "fp32_mixed", "fp32f": "fp32_fields", "fp32b": "fp32_mixed_micro_band"}
+ERR_BOUND = {"fp64": 1e-12, "fp32": 1e-5, "fp32f": 1e-6, "fp32b": 1e-5}
+MICRO_BAND = 2.0 ** -18  # eps32_micro of the "fp32b" leg: the float32-mixed tracer with the micro tie band on
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--substeps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--paths", default="fp64,fp32,fp32f", help="tracer paths to time (fp64 is the headline)")
+    ap.add_argument("--paths", default="fp64,fp32,fp32b,fp32f",
+                    help="tracer paths timed on the shell and the swirl (fp64 is the headline)")
+    ap.add_argument("--no-swirl", action="store_true")
     ap.add_argument("--no-diffusion", action="store_true")
     ap.add_argument("--no-plume", action="store_true")
-    ap.add_argument("--no-shell", action="store_true", help="skip the 1.7e8-particle spherical shell")
+    ap.add_argument("--no-elem-cache", action="store_true",
+                    help="trace without the per-lane element cache (options.elem_cache = 0)")
+    ap.add_argument("--surrogate-only", action="store_true", help="only the surrogate legs")
+    ap.add_argument("--shell-only", action="store_true",
+                    help="only the shell legs of --paths, no oracle (for profiling their kernels)")
     ap.add_argument("--diffusion-only", action="store_true",
                     help="only the advection-diffusion sub-result (for profiling its kernels)")
     ap.add_argument("--spmv-only", action="store_true",
@@ -135,19 +177,27 @@ def main():
     if args.spmv_only:
         print(json.dumps({"spmv": spmv_roofline()}), flush=True)
         return
-    wl = W.swirl3d()
     S = args.substeps
-    results = {}
+    global ELEM_CACHE
+    ELEM_CACHE = 0 if args.no_elem_cache else 1
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": time_surrogate(S, {})}), flush=True)
+        return
     paths = args.paths.split(",")
     if "fp64" not in paths:
         paths = ["fp64"] + paths
-    for path in paths:
-        results[path] = time_path(wl, path, S, args.steps, args.warmup)
-    N = results["fp64"]["N"]
-    r = results["fp64"]
-    fpp = flops_per_particle(3, 2, S)
-    bpp64 = bytes_per_particle(3, 2, 8)
+    wl3 = W.shell3d()
+    shell = time_shell(wl3, paths, S, args.steps, args.warmup,
+                       oracle=not (args.no_cpu_baseline or args.shell_only))
+    r = shell["fp64"]
+    N = shell["particles"]
+    if args.shell_only:
+        print(json.dumps({"shell3d": shell}), flush=True)
+        return
+    fpp = flops_per_particle(3, 1, S, blend=True)
+    bpp64 = bytes_per_particle(3, 1, 8)
     achieved = fpp * N / (r["kernel_ms"] * 1e-3)
+    cs = counter_summary() or {}
     out = {
         "metric": "particles traced/sec (RK4+locate+P2 interp) at stated error; FP32/MLP vs FP64",
         "value": r["value"],
@@ -161,48 +211,213 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "swirl3d: unit cube, 6 Kuhn macro tets, level 5, 274625 P2 particles, LeVeque swirl "
-                               "T=1.5, dt=T/20 (CFL~5), RK4 with %d sub-steps, 50-step run" % S,
+        "config": {"workload": "shell3d: thick spherical shell r in [0.55,1], 3840 icosahedral macro tets with radial "
+                               "blending, level 5, 168428034 P2 particles; stationary velocity of 16 seeded "
+                               "toroidal/poloidal modes (l<=8); step at r=0.8 plus 1%% noise; dt = 5 h_min/max|u|; "
+                               "RK4 with %d sub-steps; scalar ingestion + trace per step" % S,
                    "particles": N, "substeps": S, "precision": "fp64", "error_bound_vs_oracle": 1e-12},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VALU,
                      "traffic": traffic_entry(),
-                     "kernel": "trace_fp64_kernel<3,2,0>", "kernel_ms": r["kernel_ms"], "flop_per_particle": fpp,
+                     "kernel": "trace_fp64_kernel<3,1,1,double,false,2> (shell, float64)",
+                     "kernel_ms": r["kernel_ms"], "flop_per_particle": fpp, "bytes_per_particle": bpp64,
                      "hbm_GBps_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / 1e9,
                      "hbm_frac_algorithmic": bpp64 * N / (r["kernel_ms"] * 1e-3) / PEAK_HBM,
                      "hbm_GBps_measured": (traffic_entry() / (r["kernel_ms"] * 1e-3) / 1e9
                                            if traffic_entry() is not None else None),
-                     "l1_tag_lookups_per_cu_cycle": (counter_summary() or {}).get("l1_tag_lookups_per_cu_cycle")},
+                     "l1_tag_lookups_per_cu_cycle": cs.get("l1_tag_lookups_per_cu_cycle")},
         "trace_only_particles_per_s": N / (r["kernel_ms"] * 1e-3),
         "stats": r["stats"],
     }
-    if "fp32" in results:
-        f = results["fp32"]
-        out["fp32_mixed"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "kernel_ms": f["kernel_ms"],
-                             "trace_only_particles_per_s": N / (f["kernel_ms"] * 1e-3),
-                             "speedup_vs_fp64_step": f["value"] / r["value"],
-                             "speedup_vs_fp64_trace": r["kernel_ms"] / f["kernel_ms"],
-                             "error_bound_vs_oracle": 1e-5,
-                             "tieband_fraction": f["stats"]["n_tieband"] / max(1, f["stats"]["n_particles"])}
-    if "fp32f" in results:
-        f = results["fp32f"]
-        out["fp32_fields"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "kernel_ms": f["kernel_ms"],
-                              "trace_only_particles_per_s": N / (f["kernel_ms"] * 1e-3),
-                              "speedup_vs_fp64_step": f["value"] / r["value"],
-                              "speedup_vs_fp64_trace": r["kernel_ms"] / f["kernel_ms"],
-                              "error_bound_vs_oracle": 1e-6,
-                              "note": "float32 field records, float64 arithmetic"}
+    for path in paths:
+        if path != "fp64":
+            f = shell[path]
+            out[NAMES[path]] = dict(f, speedup_vs_fp64_step=f["value"] / r["value"],
+                                    speedup_vs_fp64_trace=r["kernel_ms"] / f["kernel_ms"])
+    if "error_vs_oracle" in shell:
+        out["error_vs_oracle"] = shell["error_vs_oracle"]
+    swirl = {}
+    if not args.no_swirl:
+        wl = W.swirl3d()
+        for path in paths:
+            log("swirl3d: %s" % path)
+            swirl[path] = time_path(wl, path, S, args.steps, args.warmup)
+        out["swirl3d"] = {"workload": "swirl3d: unit cube, 6 Kuhn macro tets, level 5, 274625 P2 particles, LeVeque "
+                                      "swirl T=1.5, dt=T/20 (CFL~5), RK4 with %d sub-steps, 50-step run; velocity "
+                                      "level + scalar ingestion and trace per step" % S,
+                          "particles": swirl["fp64"]["N"],
+                          "roofline_fp64_trace": {
+                              "flop_per_particle": flops_per_particle(3, 2, S),
+                              "frac": flops_per_particle(3, 2, S) * swirl["fp64"]["N"]
+                              / (swirl["fp64"]["kernel_ms"] * 1e-3) / PEAK_FP64_VALU}}
+        for path in paths:
+            f = dict(swirl[path])
+            f.pop("N")
+            f["trace_only_particles_per_s"] = swirl["fp64"]["N"] / (f["kernel_ms"] * 1e-3)
+            f["error_bound_vs_oracle"] = ERR_BOUND[path]
+            if path != "fp64":
+                f["speedup_vs_fp64_step"] = f["value"] / swirl["fp64"]["value"]
+            out["swirl3d"][NAMES[path]] = f
     if not args.no_surrogate:
-        out["surrogate"] = time_surrogate(wl, S, min(args.steps, 50), min(args.warmup, 5), results)
+        log("surrogate")
+        out["surrogate"] = time_surrogate(S, swirl)
     if not args.no_plume:
+        log("plume3d")
         out["plume3d"] = time_large(W.plume3d(), 120, ("fp64", "fp32", "fp32f"))
-    if not args.no_shell:
-        out["shell3d"] = time_large(W.shell3d(), 0, ("fp32", "fp32f"))
     if not args.no_diffusion:
+        log("diffusion")
         out["diffusion"] = time_diffusion()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, S)
+    if "cpu_baseline" in shell:
+        out["cpu_baseline"] = shell["cpu_baseline"]
     print(json.dumps(out), flush=True)
+
+
+def shell_fields(wl):
+    """The shell's velocity and initial scalar at the library's DoF positions
+    (the seeded generators, evaluated on the GPU), unique order."""
+    import torch
+    from paper_2103_02388_amd import mmoc
+    tr = mmoc.Tracer.from_workload(wl, precision=mmoc.MMOC_FP64)
+    xt = tr.dof_coords().t().contiguous()
+    tr.close()
+    u = wl.velocity(xt).t().contiguous()
+    c = wl.scalar0(xt).contiguous()
+    del xt
+    torch.cuda.empty_cache()
+    return u, c
+
+
+def time_shell(wl, paths, S, steps, warmup, oracle=True):
+    """The shell's time loop per tracer path: warm-up steps, then `steps`
+    timed steps (scalar ingestion + trace), HIP events around every trace
+    launch.  With `oracle`, the first step of every path is compared with
+    the CPU oracle on a seeded subset of SUBSET particles, and the oracle's
+    time for that subset is the CPU baseline."""
+    import torch
+    from paper_2103_02388_amd import mmoc
+
+    log("shell: evaluating the fields")
+    u, c = shell_fields(wl)
+    N = c.numel()
+    out = {"workload": wl.description, "level": wl.level, "particles": N}
+    ids = np.sort(np.random.default_rng(7).choice(N, SUBSET, replace=False))
+    first = {}
+    for path in paths:
+        log("shell: %s context" % path)
+        tr = mmoc.Tracer.from_workload(wl, precision=getattr(mmoc, PREC[path]), options=options(path))
+        assert tr.N == N
+        tr.set_stationary(True)
+        tr.set_velocity(0, u)
+        cur = c.clone()
+        chat = torch.empty(N, dtype=tr.scalar_dtype, device="cuda")
+        X = torch.empty((3, N), dtype=torch.float64, device="cuda")
+        same = chat.dtype == torch.float64
+        if oracle:
+            tr.set_scalar(c)
+            mmoc.mmoc_trace_step(tr.ctx, wl.dt, S, chat, X)
+            idt = torch.from_numpy(ids).cuda()
+            first[path] = (chat[idt].double().cpu().numpy(), X[:, idt].cpu().numpy(),
+                           tr.dof_coords()[:, idt].cpu().numpy())
+            del idt
+        state = {"cur": cur, "chat": chat}
+
+        def step(ev=None):
+            tr.set_scalar(state["cur"])
+            if ev is not None:
+                ev[0].record()
+            mmoc.mmoc_trace_step(tr.ctx, wl.dt, S, state["chat"], X)
+            if ev is not None:
+                ev[1].record()
+            if same:
+                state["cur"], state["chat"] = state["chat"], state["cur"]
+            else:
+                state["cur"].copy_(state["chat"])
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        tr.reset_stats()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for k in range(steps):
+            step(evs[k])
+        e1.record()
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        ms = max(wall_ms, e0.elapsed_time(e1)) / steps
+        kern = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        st = {k: (int(v) if isinstance(v, (int, np.integer)) else float(v)) for k, v in tr.stats().items()}
+        entry = {"value": N / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": kern,
+                 "trace_only_particles_per_s": N / (kern * 1e-3), "error_bound_vs_oracle": ERR_BOUND[path],
+                 "stats": st}
+        if path in ("fp32", "fp32b"):
+            entry["tieband_fraction"] = st["n_tieband"] / max(1, st["n_particles"])
+        out[path] = entry
+        log("shell: %s %.3f ms per step, trace %.3f ms" % (path, ms, kern))
+        tr.close()
+        del cur, chat, X, state
+        torch.cuda.empty_cache()
+    if oracle and "fp64" in first:
+        base, err = cpu_baseline_shell(wl, u, c, S, ids, first)
+        out["cpu_baseline"] = base
+        out["error_vs_oracle"] = err
+    return out
+
+
+def cpu_baseline_shell(wl, u, c, S, ids, first):
+    """The CPU oracle (float64 C, unchanged) on the seeded subset `ids` of the
+    shell's first step, with the same input arrays as the GPU: timed on all
+    host cores (disjoint particle ranges, one thread each, at most 16: the
+    GPU's share of the host) and on one core; its result also gives every
+    path's measured error on the subset."""
+    from oracle import oracle as O
+
+    log("oracle: shell mesh")
+    t0 = time.perf_counter()
+    om = O.Mesh.from_workload(wl)
+    xc = om.dof_coords()
+    setup_s = time.perf_counter() - t0
+    uh = u.cpu().numpy()
+    ch = c.cpu().numpy()
+    n = len(ids)
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    reps, tot = 0, 0.0
+    while reps == 0 or (tot < 5.0 and reps < 20):
+        t0 = time.perf_counter()
+        chr_, Xr, st = om.trace(uh, None, ch, wl.dt, S, ids=ids, threads=threads)
+        tot += time.perf_counter() - t0
+        reps += 1
+    multi = n * reps / tot
+    log("oracle: %d threads %.3g particles/s" % (threads, multi))
+    t0 = time.perf_counter()
+    om.trace(uh, None, ch, wl.dt, S, ids=ids, threads=1)
+    t1 = time.perf_counter() - t0
+    single = n / t1
+    try:
+        cpu = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        cpu = "unknown"
+    base = {"value": multi, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": "seeded subset of %d of the shell's 168428034 particles, first step (RK4 %d sub-steps, "
+                      "float64), %d repetitions on %d threads (disjoint ranges); host CPU: %s, %d logical cores"
+                      % (n, S, reps, threads, cpu, os.cpu_count() or 0),
+            "seconds": tot,
+            "one_core": {"value": single, "cores": 1, "sample": "the same %d particles, one thread" % n,
+                         "seconds": t1},
+            "oracle_mesh_setup_seconds": setup_s}
+    err = {"subset": n, "dof_coords_max_abs": float(np.abs(first["fp64"][2] - xc[:, ids]).max())}
+    # the step scalar has O(1) jumps at r = 0.8: chat is compared where the
+    # departure point is not within 0.02 of the jump (the size of a micro
+    # element there), beside the plain maximum
+    far = np.abs(np.linalg.norm(Xr, axis=0) - 0.8) > 0.02
+    for path, (chg, Xg, _) in first.items():
+        err[NAMES[path]] = {"X_rel": float(np.abs(Xg - Xr).max() / max(1.0, np.abs(Xr).max())),
+                            "chat_max_abs": float(np.abs(chg - chr_).max()),
+                            "chat_max_abs_off_step": float(np.abs(chg - chr_)[far].max())}
+    return base, err
 
 
 def time_path(wl, path, S, steps, warmup):
@@ -210,8 +425,7 @@ def time_path(wl, path, S, steps, warmup):
     from paper_2103_02388_amd import mmoc
     from paper_2103_02388_amd import workloads as W
 
-    prec = {"fp64": mmoc.MMOC_FP64, "fp32": mmoc.MMOC_FP32_MIXED, "fp32f": mmoc.MMOC_FP32_FIELDS}[path]
-    tr = mmoc.Tracer.from_workload(wl, precision=prec)
+    tr = mmoc.Tracer.from_workload(wl, precision=getattr(mmoc, PREC[path]), options=options(path))
     N = tr.N
     x = tr.dof_coords()
     xt = x.t().contiguous()
@@ -267,65 +481,106 @@ def time_path(wl, path, S, steps, warmup):
     return {"N": N, "value": N / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": kern, "stats": st}
 
 
-def time_surrogate(wl, S, steps, warmup, results):
-    """Steps 1-10 of the run traced by RK4 and recorded, 2e6 pairs sampled,
-    30 epochs of training; then steps 11-20 (cycled) with the surrogate (1%
-    check sample, tolerance 1e-4, float32-fields RK4 check and fallback)."""
+def surrogate_run(wl, vel, train, run, box_hi, U, period, prec_name="fp64", S=4, tol=1e-4, pred=1, scale=1e-4,
+                  scalar=None):
+    """The learned flow-map surrogate in a time loop (the run of config 4):
+    steps `train` (step n covers [t_{n-1}, t_n]) traced by RK4 with S
+    sub-steps and recorded, the network trained on 2e6 pairs drawn from
+    them (30 epochs), then steps `run` with the surrogate step (1% check
+    sample, tolerance tol, per-tile fallback).  The network corrects the
+    RK4 trace with `pred` sub-steps; its time input is the phase t mod
+    `period` (0: t).  The velocity levels of every run step are resident in
+    device memory before timing; one timed step is the ingestion of the new
+    velocity level and the scalar plus the surrogate step.  The plain RK4
+    step with S sub-steps of the same context is timed on the same steps."""
     import torch
     from paper_2103_02388_amd import mmoc
-    from paper_2103_02388_amd import workloads as W
 
-    tr = mmoc.Tracer.from_workload(wl, precision=mmoc.MMOC_FP32_FIELDS)
-    N = tr.N
-    tr.mlp_configure([0, 0, 0, 0], [1, 1, 1, W.SWIRL_T], 2.0)
-    x = tr.dof_coords()
-    xt = x.t().contiguous()
-    U = torch.stack([W.swirl_velocity(xt, n * wl.dt).t().contiguous() for n in range(21)])
-    c0 = W.two_blobs(xt).contiguous()
-    tr.set_scalar(c0)
-    for n in range(10):
-        tr.set_velocity(0, U[n])
-        tr.set_velocity(1, U[n + 1])
-        _, X = tr.trace_step(wl.dt, S)
-        tr.mlp_record((n + 1) * wl.dt, wl.dt, X, 10 * N)
+    tr = mmoc.Tracer.from_workload(wl, precision=getattr(mmoc, PREC[prec_name]))
+    N, dt = tr.N, wl.dt
+    tr.mlp_configure([0, 0, 0, 0], [1, 1, 1, box_hi], U)
+    tr.mlp_set_predictor(pred, scale, period)
+    xt = tr.dof_coords().t().contiguous()
+    c0 = (scalar or wl.scalar0)(xt).contiguous()
+    levels = {n: vel(xt, n * dt).t().contiguous() for n in range(min(train) - 1, max(run) + 1)}
+    del xt
+    cur = c0.clone()
+    for n in train:
+        tr.set_velocity(0, levels[n - 1])
+        tr.set_velocity(1, levels[n])
+        tr.set_scalar(cur)
+        ch, X = tr.trace_step(dt, S)
+        tr.mlp_record(n * dt, dt, X, len(train) * N)
+        cur = ch.double() if ch.dtype != torch.float64 else ch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     loss = tr.mlp_train(2_000_000, 30, batch=8192, lr=1e-3, seed=5)
     t_train = time.perf_counter() - t0
-    chat = torch.empty(N, dtype=torch.float32, device="cuda")
+    chat = torch.empty(N, dtype=tr.scalar_dtype, device="cuda")
     X = torch.empty((3, N), dtype=torch.float64, device="cuda")
-    cur = c0.clone()
+    runs = list(run)
 
-    def step(k):
-        n = 10 + k % 10
-        tr.set_velocity(0, U[n])
-        tr.set_velocity(1, U[n + 1])
-        tr.set_scalar(cur)
-        mmoc.mmoc_trace_step_surrogate(tr.ctx, (n + 1) * wl.dt, wl.dt, S, 0.01, 1e-4, n, chat, X)
-        cur.copy_(chat)
+    def loop(surrogate):
+        c = c0.clone()
+        tr.set_velocity(1, levels[runs[0] - 1])
+        rk4 = []
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in runs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, n in enumerate(runs):
+            tr.swap_levels()
+            tr.set_fields(1, levels[n], c)
+            if surrogate:
+                tr.reset_stats()
+            ev[k][0].record()
+            if surrogate:
+                mmoc.mmoc_trace_step_surrogate(tr.ctx, n * dt, dt, S, 0.01, tol, n, chat, X)
+            else:
+                mmoc.mmoc_trace_step(tr.ctx, dt, S, chat, X)
+            ev[k][1].record()
+            if surrogate:
+                st = tr.stats()  # synchronises: the per-step fraction traced by RK4
+                rk4.append((st["n_checked"] + st["n_fallback"]) / N)
+            c.copy_(chat)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / len(runs)
+        return float(np.mean([a.elapsed_time(b) for a, b in ev])), wall, rk4
 
-    for k in range(warmup):
-        step(k)
-    torch.cuda.synchronize()
-    tr.reset_stats()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        step(k)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    st = tr.stats()
+    loop(True)  # warm-up pass
+    sur_ms, sur_wall, rk4 = loop(True)
+    rk_ms, rk_wall, _ = loop(False)
     tr.close()
-    fb = (st["n_checked"] + st["n_fallback"]) / (N * steps)
-    out = {"value": N / (ms * 1e-3), "ms_per_step": ms, "train_seconds": t_train, "final_loss": loss,
-           "rk4_fraction": fb, "max_check_residual": st["max_check_residual"], "tolerance": 1e-4,
-           "note": "steps 11-20 (cycled) of the swirl run; the network is trained on steps 1-10; "
-                   "check sample and fallback traced by the float32-fields RK4 tracer"}
-    if "fp64" in results:
-        out["speedup_vs_fp64_step"] = out["value"] / results["fp64"]["value"]
-    if "fp32" in results:
-        out["speedup_vs_fp32_step"] = out["value"] / results["fp32"]["value"]
-    if "fp32f" in results:
-        out["speedup_vs_fp32_fields_step"] = out["value"] / results["fp32f"]["value"]
+    kept = [f for f in rk4 if f < 0.5]
+    return {"precision": prec_name, "train_steps": [min(train), max(train)], "run_steps": [min(run), max(run)],
+            "tolerance": tol, "predictor_substeps": pred, "correction_scale": scale, "time_period": period,
+            "train_seconds": t_train, "final_loss": loss,
+            "surrogate_ms": sur_ms, "rk4_ms": rk_ms,
+            "speedup_vs_rk4_same_precision": rk_ms / sur_ms,
+            "rk4_fraction_mean": float(np.mean(rk4)), "rk4_fraction_max": float(np.max(rk4)),
+            "steps_keeping_the_network": len(kept), "steps": len(rk4),
+            "rk4_fraction_per_step": [round(f, 4) for f in rk4],
+            "note": "ms are HIP-event means of the step call (surrogate: predictor, network, check on a second "
+                    "stream, residuals, finish pass); the per-step statistics synchronise, so the loop's wall "
+                    "time is not the rate"}
+
+
+def time_surrogate(S, swirl):
+    """Config 4 on the swirl (trained on steps 1-10, steps 11-110) and its
+    full-period variant (trained on steps 1-40, one period of the velocity;
+    steps 41-140); config 5's surrogate leg on the rising plumes (trained on
+    steps 1-10, steps 11-200)."""
+    from paper_2103_02388_amd import workloads as W
+    wl = W.swirl3d(steps=140)
+    per = 2.0 * W.SWIRL_T
+    out = {"swirl3d_config4": surrogate_run(wl, W.swirl_velocity, range(1, 11), range(11, 111), per, 2.0, per, S=S),
+           "swirl3d_full_period": surrogate_run(wl, W.swirl_velocity, range(1, 41), range(41, 141), per, 2.0, per,
+                                                S=S)}
+    if "fp64" in swirl:
+        for k in ("swirl3d_config4", "swirl3d_full_period"):
+            out[k]["speedup_vs_fp64_swirl_trace"] = swirl["fp64"]["kernel_ms"] / out[k]["surrogate_ms"]
+    pl = W.plume3d()
+    out["plume3d_config5"] = surrogate_run(pl, pl.velocity, range(1, 11), range(11, 201), pl.extra["T"],
+                                           pl.extra["umax"], 0.0, S=S)
     return out
 
 
@@ -489,36 +744,6 @@ def spmv_roofline():
             "dofs": bN, "nnz": bnnz, "kernel_ms": big_ms, "bytes_per_launch": spmv_bytes(bN, bnnz),
             "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": achieved / PEAK_HBM,
             "traffic": None}
-
-
-def cpu_baseline(wl, S):
-    """The CPU oracle (unchanged, single-threaded) on the same step's
-    particles with its own copy of the same inputs: full steps repeated until
-    about 10 s of single-core work."""
-    import torch
-    from oracle import oracle as O
-    from paper_2103_02388_amd import workloads as W
-
-    om = O.Mesh.from_workload(wl)
-    xc = om.dof_coords()
-    xt = torch.from_numpy(np.ascontiguousarray(xc.T))
-    u0 = np.ascontiguousarray(W.swirl_velocity(xt, 7 * wl.dt).numpy().T)
-    u1 = np.ascontiguousarray(W.swirl_velocity(xt, 8 * wl.dt).numpy().T)
-    c = W.two_blobs(xt).numpy()
-    reps, total = 0, 0.0
-    while reps == 0 or (total < 10.0 and reps < 40):
-        t0 = time.perf_counter()
-        om.trace(u0, u1, c, wl.dt, S, threads=1)
-        total += time.perf_counter() - t0
-        reps += 1
-    try:
-        cpu = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
-    except Exception:
-        cpu = "unknown"
-    return {"value": om.N * reps / total, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": "%d x %d particles: the full swirl3d step 7 -> 8 repeated, RK4 %d sub-steps, float64, "
-                      "single thread; host CPU: %s (%d logical cores)" % (reps, om.N, S, cpu, os.cpu_count() or 0),
-            "seconds": total}
 
 
 if __name__ == "__main__":

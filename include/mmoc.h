@@ -93,7 +93,11 @@ typedef struct {
     int order;         /* element order of the fields and DoFs: 2 = P2 (default; 0 also
                           means 2), 1 = P1, the micro vertices (Sec. 3.1: P1 and P2
                           Lagrange elements).  P1 is not built for blended meshes. */
-    int reserved[3];
+    int elem_cache;    /* 1 (default): each lane keeps the nodal velocities of its last
+                          micro element in LDS and gathers only when the element changes
+                          (stationary runs and float32 records, within one step); 0: gather
+                          at every stage.  Results are bitwise the same either way. */
+    int reserved[2];
 } mmoc_options;
 
 typedef struct {
@@ -107,6 +111,8 @@ typedef struct {
     int64_t n_checked;     /* surrogate: particles re-traced by RK4 as the check sample */
     int64_t n_fallback;    /* surrogate: particles whose result came from the RK4 fallback */
     double max_check_residual; /* surrogate: largest |Xhat - X_rk4|_inf over the check sample */
+    int64_t n_cache_lookups;   /* stage evaluations through the element cache */
+    int64_t n_cache_hits;      /* ... of which found their element's values in it */
 } mmoc_stats;
 
 /* Fills *opt with the defaults listed above. */
@@ -257,23 +263,41 @@ mmoc_status mmoc_lookback_run(mmoc_ctx* ctx, double tau, int substeps, int64_t n
                               double* ring_dev, int64_t ring_len, double* c_out_dev);
 
 /* ---------------- learned flow-map surrogate (not part of the paper) -------
- * An MLP (x, t_{n+1}) -> scaled displacement, 4 -> 64 -> 64 -> 64 -> 3 with
+ * An MLP (x, t) -> scaled displacement, 4 -> 64 -> 64 -> 64 -> 3 with
  * tanh-form GELU (Hendrycks & Gimpel 2016), bf16 weights and activations,
  * fp32 accumulation on the matrix cores.  Inputs are affinely scaled to
- * [-1,1] (box [lo, hi] per input), the output is (X - x) / (dt * U).
+ * [-1,1] (box [lo, hi] per input).  Without a predictor the output is the
+ * whole displacement (X - x) / (dt * U); with a predictor
+ * (mmoc_mlp_set_predictor) it is the correction (X - X_p) / scale to the
+ * departure point X_p of the context's own RK4 tracer with fewer sub-steps.
  * Parameters are a flat float32 vector of mmoc_mlp_nparams() entries, layer
  * by layer: W1 [64][4], b1 [64], W2 [64][64], b2 [64], W3 [64][64], b3 [64],
- * W4 [3][64], b4 [3] (W[out][in]). */
+ * W4 [3][64], b4 [3] (W[out][in]).  The surrogate is built for unblended 3D
+ * meshes (MMOC_E_UNSUPPORTED otherwise). */
 
 int64_t mmoc_mlp_nparams(void);
 
-/* Input box: lo[4], hi[4] for (x, y, z, t); output scale U > 0. */
+/* Input box: lo[4], hi[4] for (x, y, z, t); output scale U > 0 of the
+ * whole-displacement form.  Allocates the surrogate's state (parameters
+ * seeded, Adam moments zero) on the first call. */
 mmoc_status mmoc_mlp_configure(mmoc_ctx* ctx, const double* lo, const double* hi, double U);
 
-/* Appends training pairs: the current DoF positions with time t_np1 as
- * inputs and X_dev (SoA [dim][n_unique] float64, a step of length dt) as
- * targets.  Buffers up to `capacity` pairs (set by the first call; library
- * owned device memory). */
+/* The predictor the network corrects and its time input.  substeps in
+ * [1, 64]: X_p is the context's RK4 trace of the step with that many
+ * sub-steps (the fields of the step must be set when recording, inferring
+ * and stepping), and the network's output is (X - X_p) / scale, scale > 0
+ * (a length).  substeps 0: no predictor (the default; scale is ignored).
+ * period > 0: the time input is the phase t mod period (a velocity periodic
+ * in time); 0: t itself (the default).  Must be set before the first pair
+ * is recorded (MMOC_E_STATE if pairs were recorded with another setting). */
+mmoc_status mmoc_mlp_set_predictor(mmoc_ctx* ctx, int substeps, double scale, double period);
+
+/* Appends training pairs for the step just traced: the DoF positions with
+ * time t_np1 as inputs and X_dev (SoA [dim][n_unique] float64, the step's
+ * departure points, a step of length dt) as targets, expressed as the
+ * network's output (with a predictor, the predictor is traced through the
+ * context's current fields to form the correction).  Buffers up to
+ * `capacity` pairs (set by the first call; library owned device memory). */
 mmoc_status mmoc_mlp_record(mmoc_ctx* ctx, double t_np1, double dt, const double* X_dev,
                             int64_t capacity);
 
@@ -302,18 +326,23 @@ mmoc_status mmoc_mlp_loss_grad(mmoc_ctx* ctx, const float* in_dev, const float* 
 mmoc_status mmoc_mlp_get_weights(mmoc_ctx* ctx, float* host_params, int64_t n);
 mmoc_status mmoc_mlp_set_weights(mmoc_ctx* ctx, const float* host_params, int64_t n);
 
-/* Surrogate inference for all particles: Xhat_i = x_i + dt U MLP(x_i, t_np1),
- * written to X_dev (SoA [dim][n_unique] float64). */
+/* Surrogate departure points for all particles, written to X_dev (SoA
+ * [dim][n_unique] float64): Xhat_i = x_i + dt U MLP(x_i, t_np1), or with a
+ * predictor Xhat_i = X_p,i + scale MLP(x_i, t_np1). */
 mmoc_status mmoc_mlp_infer(mmoc_ctx* ctx, double t_np1, double dt, double* X_dev);
 
-/* Surrogate step: inference for all particles, then an RK4 re-trace (the
- * context's own tracer and precision, same fields) of a seeded sample of about check_fraction of
- * the particles (hash(seed, step, i) < check_fraction, with at least one per
- * tile of 128 particles); every checked particle keeps its RK4 result, and
- * every particle of a tile in which some checked residual
- * |Xhat - X_rk4|_inf exceeds tol/2 is re-traced by RK4 (fallback).
- * Then chat = c_h^n(X) as in mmoc_trace_step.  c_hat_dev: double* for
- * MMOC_FP64 contexts, float* otherwise.  step seeds the sample. */
+/* Surrogate step.  The departure points of all particles come from the
+ * network (mmoc_mlp_infer).  A seeded sample of about check_fraction of the
+ * particles (hash(seed, step, i) < check_fraction, with at least one per
+ * tile of 128 consecutive particles) is re-traced by RK4 with `substeps`
+ * sub-steps by the context's own tracer and precision, on the same fields
+ * (on a second stream, beside the network).  Every checked particle keeps
+ * its RK4 result; every particle of a tile in which some checked residual
+ * |Xhat - X_rk4|_inf exceeds tol/2 is re-traced by RK4 (fallback).  Then
+ * chat = c_h^n(X) as in mmoc_trace_step.  c_hat_dev: double* for MMOC_FP64
+ * contexts, float* otherwise.  step seeds the sample.  Statistics:
+ * n_checked, n_fallback (unchecked particles of fallback tiles) and
+ * max_check_residual; n_particles counts traced and evaluated lanes. */
 mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* ctx, double t_np1, double dt, int substeps,
                                       float check_fraction, double tol, int64_t step,
                                       void* c_hat_dev, double* X_dev);

@@ -66,8 +66,17 @@ mmoc_status mmoc_check_step_args(mmoc_ctx* c, double dt, int substeps, void* c_h
 // traces DoF t); n_dev (optional) is a device-side count that bounds the lanes
 // Each particle is traced from logical velocity level first + n_int back to
 // level first, n_int intervals of length dt with `substeps` RK sub-steps each.
+// Optional launch settings: the stream (null: the context's) and the
+// surrogate finish (TraceArgs::checked / xcheck / tol_half).
+struct TraceExtra {
+    hipStream_t stream = nullptr;
+    const unsigned char* checked = nullptr;
+    const double* xcheck = nullptr;
+    double tol_half = 0.0;
+};
 mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* order,
-                              int64_t n, const unsigned long long* n_dev = nullptr, int first = 0, int n_int = 1);
+                              int64_t n, const unsigned long long* n_dev = nullptr, int first = 0, int n_int = 1,
+                              const TraceExtra* ex = nullptr);
 // physical ring slot of logical velocity level l
 inline int phys_level(const mmoc_ctx* c, int l) { return (c->rot + l) % c->lev_cap; }
 void mmoc_mlp_free_state(mmoc_ctx* c);

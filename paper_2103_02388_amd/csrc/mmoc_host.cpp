@@ -42,8 +42,12 @@ mmoc_status fail(mmoc_ctx* c, mmoc_status st, const char* fmt, ...)
     return st;
 }
 
+// A failed runtime call also leaves its error as the thread's last HIP
+// error, which the next launch check would report again: it is consumed here,
+// once it has been returned to the caller.
 mmoc_status hip_fail(mmoc_ctx* c, hipError_t e, const char* what)
 {
+    (void)hipGetLastError();
     return fail(c, e == hipErrorOutOfMemory ? MMOC_E_NOMEM : MMOC_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -201,6 +205,7 @@ void mmoc_default_options(mmoc_options* o)
     o->eps32_micro = 0.0f;  // micro ties are value-neutral (P2 is continuous across micro faces)
     o->max_hops = 64;
     o->order = 2;
+    o->elem_cache = 1;
 }
 
 mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec, const mmoc_options* opt,
@@ -212,7 +217,7 @@ mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec,
     if (level < 0 || level > 10 || (dim == 3 && level > 9)) return MMOC_E_ARG;  // lattice index fits int32
     if (prec != MMOC_FP64 && prec != MMOC_FP32_MIXED && prec != MMOC_FP32_FIELDS) return MMOC_E_ARG;
     if (opt && (!(opt->eps_in >= 0) || opt->max_hops < 0 || !(opt->eps32_macro >= 0) || !(opt->eps32_micro >= 0) ||
-                opt->order < 0 || opt->order > 2))
+                opt->order < 0 || opt->order > 2 || opt->elem_cache < 0 || opt->elem_cache > 1))
         return MMOC_E_ARG;
     mmoc_ctx* c = new (std::nothrow) mmoc_ctx();
     if (!c) return MMOC_E_NOMEM;
@@ -625,8 +630,9 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
 // Shared by the plain and the surrogate step: launches the RK4 tracer on n
 // particles whose unique ids are order[0..n) (all particles: the lane order).
 mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat, double* X, const int32_t* order,
-                              int64_t n, const unsigned long long* n_dev, int first, int n_int)
+                              int64_t n, const unsigned long long* n_dev, int first, int n_int, const TraceExtra* ex)
 {
+    const hipStream_t stream = ex && ex->stream ? ex->stream : c->stream;
     auto fill = [&](auto& a) {
         a.geo = c->geo_d;
         a.owned = c->owned_d;
@@ -646,6 +652,7 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.eps_in = c->opt.eps_in;
         a.eps32_macro = c->opt.eps32_macro;
         a.eps32_micro = c->opt.eps32_micro;
+        a.elem_cache = c->opt.elem_cache;
         a.X = X;
         a.stats = c->stats_d;
         a.rk = c->rk;
@@ -656,6 +663,9 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.rot = c->rot;
         a.first = first;
         a.n_int = n_int;
+        a.checked = ex ? ex->checked : nullptr;
+        a.xcheck = ex ? ex->xcheck : nullptr;
+        a.tol_half = ex ? ex->tol_half : 0.0;
     };
     if (c->prec != MMOC_FP64) {
         mmoc::TraceArgs<float> a{};
@@ -665,9 +675,9 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.cs = (const float*)c->cs_d;
         a.c_hat = (float*)c_hat;
         if (c->prec == MMOC_FP32_MIXED)
-            HIPCHK(c, mmoc::launch_trace_fp32(c->dim, c->blend, a, c->stream), "trace (fp32 mixed)");
+            HIPCHK(c, mmoc::launch_trace_fp32(c->dim, c->blend, a, stream), "trace (fp32 mixed)");
         else
-            HIPCHK(c, mmoc::launch_trace_fp32_fields(c->dim, c->blend, a, c->stream), "trace (fp32 fields)");
+            HIPCHK(c, mmoc::launch_trace_fp32_fields(c->dim, c->blend, a, stream), "trace (fp32 fields)");
     } else {
         mmoc::TraceArgs<double> a{};
         fill(a);
@@ -675,7 +685,7 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.vb = (const double*)c->vb_all;
         a.cs = (const double*)c->cs_d;
         a.c_hat = (double*)c_hat;
-        HIPCHK(c, mmoc::launch_trace_fp64(c->dim, c->blend, a, c->stream), "trace (fp64)");
+        HIPCHK(c, mmoc::launch_trace_fp64(c->dim, c->blend, a, stream), "trace (fp64)");
     }
     return MMOC_OK;
 }
@@ -766,6 +776,8 @@ mmoc_status mmoc_get_stats(mmoc_ctx* c, mmoc_stats* out)
     double r;
     std::memcpy(&r, &h[mmoc::ST_MAXRES_BITS], sizeof r);
     out->max_check_residual = r;
+    out->n_cache_lookups = (int64_t)h[mmoc::ST_CACHE_LOOKUPS];
+    out->n_cache_hits = (int64_t)h[mmoc::ST_CACHE_HITS];
     return MMOC_OK;
 }
 

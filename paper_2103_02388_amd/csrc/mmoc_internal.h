@@ -47,8 +47,15 @@ enum StatSlot {
     ST_CHECKED,
     ST_FALLBACK,
     ST_MAXRES_BITS,  // max check residual, stored as the bits of a non-negative double
+    ST_CACHE_LOOKUPS,  // stage evaluations that went through the element cache
+    ST_CACHE_HITS,     // ... and found their element in it
     ST_COUNT
 };
+
+// Tile of the surrogate's check and fallback: 128 consecutive particles in
+// unique order, which is one block of the trace kernels (the finish pass
+// branches per block).
+constexpr int kSurrogateTile = 128;
 
 enum LaneFlag : unsigned {
     LF_OUTSIDE = 1u,
@@ -56,6 +63,7 @@ enum LaneFlag : unsigned {
     LF_BRUTE = 4u,
     LF_TIEBAND = 8u,
     LF_NAN = 16u,
+    LF_FALLBACK = 32u,  // surrogate finish: re-traced because its tile failed the check
 };
 
 // Arguments of the trace kernels.  Fields live in per-component arrays over
@@ -109,6 +117,16 @@ struct TraceArgs {
     double eps_in;
     float eps32_macro;
     float eps32_micro;
+    int elem_cache;          // 1: keep the last element's nodal velocities per lane in LDS
+    // Surrogate finish (order must be null; a block is a tile of
+    // kSurrogateTile particles): X holds the surrogate's departure points,
+    // xcheck the RK4 ones of the particles with checked[pid] set.  A tile in
+    // which some checked residual |X - xcheck|_inf exceeds tol_half is
+    // traced (fallback); the others keep X (checked particles take xcheck)
+    // and only get the scalar.
+    const unsigned char* checked;
+    const double* xcheck;
+    double tol_half;
     T* c_hat;                // [n_unique] or null
     double* X;               // [dim][n_unique] or null
     unsigned long long* stats;

@@ -38,15 +38,22 @@ struct mlp_state {
     int64_t part_tiles = 0, losses_n = 0;
     // surrogate step scratch
     int32_t* ids = nullptr;
-    unsigned long long* n_ids = nullptr;  // [2]: check list, fallback list
+    unsigned long long* n_ids = nullptr;  // [2]: the check list's length (second entry unused)
     unsigned char* checked = nullptr;
-    unsigned char* tile_flag = nullptr;
-    double* Xrk = nullptr;
+    double* Xrk = nullptr;  // check points; the predictor's points while recording
+    // predictor: the network learns the correction to the context's own RK4
+    // trace with pred_substeps sub-steps (0: the whole displacement)
+    int pred_substeps = 0;
+    double corr_scale = 1.0;  // output scale of the correction
+    double period = 0.0;      // > 0: the time input is t mod period
+    // the check's RK4 trace runs on a second stream beside the network
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
 
-constexpr int kTile = 128;
+constexpr int kTile = mmoc::kSurrogateTile;
 
 MlpArgs args_of(mmoc_ctx* c)
 {
@@ -117,6 +124,36 @@ std::vector<float> init_params(uint64_t seed)
     return p;
 }
 
+// the network's time input: t, or its phase t mod period
+double time_input(const mlp_state* S, double t)
+{
+    return S->period > 0 ? t - S->period * std::floor(t / S->period) : t;
+}
+
+// the velocity levels of a step are set (the predictor traces through them)
+mmoc_status need_velocity(mmoc_ctx* c)
+{
+    if (c->lev_cap < 1 || !c->vel_set[0]) return fail(c, MMOC_E_STATE, "velocity level 0 is not set");
+    if (!c->stationary && !c->vel_set[1]) return fail(c, MMOC_E_STATE, "velocity level 1 is not set");
+    return MMOC_OK;
+}
+
+// the predictor's departure points of every particle into X (no scalar)
+mmoc_status run_predictor(mmoc_ctx* c, double dt, double* X)
+{
+    return mmoc_launch_trace(c, dt, c->mlp->pred_substeps, nullptr, X, nullptr, c->N);
+}
+
+mmoc_status need_aux(mmoc_ctx* c)
+{
+    mlp_state* S = c->mlp;
+    if (S->aux) return MMOC_OK;
+    HIPCHK(c, hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking), "check stream");
+    HIPCHK(c, hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming), "check stream events");
+    HIPCHK(c, hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming), "check stream events");
+    return MMOC_OK;
+}
+
 mmoc_status need_mlp(mmoc_ctx* c)
 {
     if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
@@ -132,8 +169,11 @@ void mmoc_mlp_free_state(mmoc_ctx* c)
     mlp_state* S = c->mlp;
     if (!S) return;
     void* ptrs[] = {S->p32, S->m, S->v, S->grad, S->wbf, S->in4, S->tg3, S->sel, S->part, S->scratch, S->losses,
-                    S->ids, S->n_ids, S->checked, S->tile_flag, S->Xrk};
+                    S->ids, S->n_ids, S->checked, S->Xrk};
     for (void* p : ptrs) (void)hipFree(p);
+    if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+    if (S->ev_join) (void)hipEventDestroy(S->ev_join);
+    if (S->aux) (void)hipStreamDestroy(S->aux);
     delete S;
     c->mlp = nullptr;
 }
@@ -167,7 +207,6 @@ mmoc_status mmoc_mlp_configure(mmoc_ctx* c, const double* lo, const double* hi, 
         (st = alloc(c, &S->ids, (size_t)c->N, "surrogate lists")) != MMOC_OK ||
         (st = alloc(c, &S->n_ids, 2, "surrogate counts")) != MMOC_OK ||
         (st = alloc(c, &S->checked, (size_t)c->N, "surrogate flags")) != MMOC_OK ||
-        (st = alloc(c, &S->tile_flag, (size_t)((c->N + kTile - 1) / kTile), "surrogate flags")) != MMOC_OK ||
         (st = alloc(c, &S->Xrk, (size_t)c->N * 3, "surrogate check points")) != MMOC_OK) {
         mmoc_mlp_free_state(c);
         return st;
@@ -227,7 +266,17 @@ mmoc_status mmoc_mlp_record(mmoc_ctx* c, double t_np1, double dt, const double* 
     }
     if (S->count + c->N > S->cap) return fail(c, MMOC_E_ARG, "record buffer full (%lld pairs)", (long long)S->cap);
     MlpArgs a = args_of(c);
-    HIPCHK(c, launch_record(a, t_np1, 1.0 / (dt * S->U), X, S->in4 + S->count * 4, S->tg3 + S->count * 3, c->stream),
+    const double* Xp = nullptr;
+    double inv = 1.0 / (dt * S->U);
+    if (S->pred_substeps > 0) {
+        // the target is the correction to the predictor of the same step
+        if ((st = need_velocity(c)) != MMOC_OK) return st;
+        if ((st = run_predictor(c, dt, S->Xrk)) != MMOC_OK) return st;
+        Xp = S->Xrk;
+        inv = 1.0 / S->corr_scale;
+    }
+    HIPCHK(c, launch_record(a, time_input(S, t_np1), inv, X, Xp, S->in4 + S->count * 4, S->tg3 + S->count * 3,
+                            c->stream),
            "record");
     S->count += c->N;
     return MMOC_OK;
@@ -350,7 +399,32 @@ mmoc_status mmoc_mlp_infer(mmoc_ctx* c, double t_np1, double dt, double* X)
     if (st != MMOC_OK) return st;
     if (!(dt > 0) || !std::isfinite(t_np1)) return fail(c, MMOC_E_ARG, "need dt > 0 and a finite t");
     if ((st = check_dev(c, X, sizeof(double) * 3 * c->N, 8, "X_dev")) != MMOC_OK) return st;
-    HIPCHK(c, launch_infer(args_of(c), t_np1, dt * c->mlp->U, X, c->stream), "mlp inference");
+    mlp_state* S = c->mlp;
+    if (S->pred_substeps > 0) {
+        if ((st = need_velocity(c)) != MMOC_OK) return st;
+        if ((st = run_predictor(c, dt, X)) != MMOC_OK) return st;
+        HIPCHK(c, launch_infer(args_of(c), time_input(S, t_np1), S->corr_scale, X, 1, c->stream), "mlp inference");
+    } else {
+        HIPCHK(c, launch_infer(args_of(c), time_input(S, t_np1), dt * S->U, X, 0, c->stream), "mlp inference");
+    }
+    return MMOC_OK;
+}
+
+mmoc_status mmoc_mlp_set_predictor(mmoc_ctx* c, int substeps, double scale, double period)
+{
+    if (!c) return MMOC_E_ARG;
+    mmoc_status st = need_mlp(c);
+    if (st != MMOC_OK) return st;
+    if (substeps < 0 || substeps > 64) return fail(c, MMOC_E_ARG, "predictor sub-steps must be in [0, 64]");
+    if (substeps > 0 && !(scale > 0 && std::isfinite(scale))) return fail(c, MMOC_E_ARG, "need scale > 0");
+    if (!(period >= 0 && std::isfinite(period))) return fail(c, MMOC_E_ARG, "need period >= 0");
+    mlp_state* S = c->mlp;
+    if (S->count > 0 && (substeps != S->pred_substeps || (substeps > 0 && scale != S->corr_scale) ||
+                         period != S->period))
+        return fail(c, MMOC_E_STATE, "training pairs were recorded with another predictor or time input");
+    S->pred_substeps = substeps;
+    S->corr_scale = substeps > 0 ? scale : 1.0;
+    S->period = period;
     return MMOC_OK;
 }
 
@@ -366,57 +440,40 @@ mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* c, double t_np1, double dt, int 
     if (!(tol >= 0) || !std::isfinite(t_np1)) return fail(c, MMOC_E_ARG, "need tol >= 0 and a finite t");
     mlp_state* S = c->mlp;
     const int64_t N = c->N;
-    // 1. the network's departure points for every particle
-    HIPCHK(c, launch_infer(args_of(c), t_np1, dt * S->U, X, c->stream), "mlp inference");
-    // 2. the seeded check sample (at least one per tile)
-    HIPCHK(c, hipMemsetAsync(S->n_ids, 0, 2 * sizeof(unsigned long long), c->stream), "clear counts");
+    if ((st = need_aux(c)) != MMOC_OK) return st;
+    // The check sample's RK4 trace depends only on the fields: it runs on the
+    // auxiliary stream while the predictor and the network run on the
+    // context's stream.
+    HIPCHK(c, hipEventRecord(S->ev_fork, c->stream), "fork");
+    HIPCHK(c, hipStreamWaitEvent(S->aux, S->ev_fork, 0), "fork");
+    // 1. the seeded check sample (at least one per tile), then RK4 on it
+    HIPCHK(c, hipMemsetAsync(S->n_ids, 0, sizeof(unsigned long long), S->aux), "clear count");
     const uint64_t seed = 0x243F6A8885A308D3ull ^ ((uint64_t)step * 0x9E3779B97F4A7C15ull);
-    HIPCHK(c, launch_select_check(N, kTile, seed, check_fraction, S->ids, S->n_ids, S->checked, S->tile_flag, c->stream),
+    HIPCHK(c, launch_select_check(N, kTile, seed, check_fraction, S->ids, S->n_ids, S->checked, S->aux),
            "check sample");
-    // 3. RK4 on the sample, into the check buffer
-    if ((st = mmoc_launch_trace(c, dt, substeps, nullptr, S->Xrk, S->ids, N, S->n_ids)) != MMOC_OK) return st;
-    // 4. residuals; tiles with a residual above tol/2 fall back entirely
-    HIPCHK(c, launch_residual(c->dim, N, kTile, S->ids, S->n_ids, S->Xrk, X, tol, S->tile_flag, c->stats_d, N, c->stream),
-           "residuals");
-    HIPCHK(c, launch_fallback_list(N, kTile, S->tile_flag, S->checked, S->ids, S->n_ids + 1, c->stats_d, c->stream),
-           "fallback list");
-    // 5. RK4 for the fallback particles, straight into X
-    if ((st = mmoc_launch_trace(c, dt, substeps, nullptr, X, S->ids, N, S->n_ids + 1)) != MMOC_OK) return st;
-    // 6. the old scalar at every departure point
-    auto fill = [&](auto& a) {
-        a.geo = c->geo_d;
-        a.owned = c->owned_d;
-        a.n = N;
-        a.xstride = N;
-        a.nm = c->nm;
-        a.npm = (int)c->npm;
-        a.level_n = c->n;
-        a.ord = c->opt.order;
-        a.lat_m = c->m;
-        a.max_hops = c->opt.max_hops;
-        a.eps_in = c->opt.eps_in;
-        a.eps32_macro = c->opt.eps32_macro;
-        a.eps32_micro = c->opt.eps32_micro;
-        a.X = X;
-        a.stats = c->stats_d;
-    };
-    if (c->prec != MMOC_FP64) {
-        mmoc::TraceArgs<float> a{};
-        fill(a);
-        a.cs = (const float*)c->cs_d;
-        a.c_hat = (float*)c_hat;
-        if (c->prec == MMOC_FP32_MIXED)
-            HIPCHK(c, mmoc::launch_scalar_eval_fp32(c->dim, c->blend, a, c->stream), "scalar evaluation");
-        else
-            HIPCHK(c, mmoc::launch_scalar_eval_fp32_fields(c->dim, c->blend, a, c->stream), "scalar evaluation");
+    TraceExtra on_aux;
+    on_aux.stream = S->aux;
+    if ((st = mmoc_launch_trace(c, dt, substeps, nullptr, S->Xrk, S->ids, N, S->n_ids, 0, 1, &on_aux)) != MMOC_OK)
+        return st;
+    HIPCHK(c, hipEventRecord(S->ev_join, S->aux), "join");
+    // 2. the surrogate's departure points for every particle: the network
+    //    alone, or the predictor's trace plus the network's correction
+    if (S->pred_substeps > 0) {
+        if ((st = run_predictor(c, dt, X)) != MMOC_OK) return st;
+        HIPCHK(c, launch_infer(args_of(c), time_input(S, t_np1), S->corr_scale, X, 1, c->stream), "mlp inference");
     } else {
-        mmoc::TraceArgs<double> a{};
-        fill(a);
-        a.cs = (const double*)c->cs_d;
-        a.c_hat = (double*)c_hat;
-        HIPCHK(c, mmoc::launch_scalar_eval_fp64(c->dim, c->blend, a, c->stream), "scalar evaluation");
+        HIPCHK(c, launch_infer(args_of(c), time_input(S, t_np1), dt * S->U, X, 0, c->stream), "mlp inference");
     }
-    return MMOC_OK;
+    HIPCHK(c, hipStreamWaitEvent(c->stream, S->ev_join, 0), "join");
+    // 3. one pass over all particles, a block per tile: the tile's checked
+    //    residuals |Xhat - X_rk4|_inf decide; above tol/2 the whole tile is
+    //    traced by RK4 (fallback), otherwise it keeps Xhat (checked particles
+    //    their RK4 result); then chat = c_h^n(X)
+    TraceExtra finish;
+    finish.checked = S->checked;
+    finish.xcheck = S->Xrk;
+    finish.tol_half = 0.5 * tol;
+    return mmoc_launch_trace(c, dt, substeps, c_hat, X, nullptr, N, nullptr, 0, 1, &finish);
 }
 
 }  // extern "C"

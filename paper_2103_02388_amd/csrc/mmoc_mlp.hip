@@ -181,11 +181,118 @@ __device__ __forceinline__ void dof_pos(const MacroGeo* __restrict__ geo, uint64
 
 // ------------------------------------------------------------- inference
 
-__global__ __launch_bounds__(128) void infer_kernel(const MlpArgs A, double t_np1, double step_scale, double* X)
+// Forward pass for inference, one wave per tile of 64 samples, one block per
+// wave.  The hidden layers are computed transposed, D^T = W A^T: the weights
+// are the matrix-core A operand ([out][in], read from L1/L2) and the
+// activations the B operand ([sample][feature] in LDS), so an accumulator
+// lane holds four consecutive features of one sample and writes them to LDS
+// as one 8-byte store.  The last hidden layer stays in registers (fp32); the
+// output layer sums each lane's 16 features per sample and reduces over the
+// four lanes that share the sample.  Same bf16 rounding points as
+// forward_tile; only the fp32 order of the output sums differs.
+// One transposed hidden layer, n-tile by n-tile (16 samples at a time, so
+// that only 16 accumulators are live): epi(nt, acc) receives
+// acc[mt][i] = (W a + b)[feature mt*16 + 4g + i][sample nt*16 + r].
+template <typename Epi>
+__device__ __forceinline__ void hidden_t(const __bf16* __restrict__ W, const float* __restrict__ bias,
+                                         const __bf16* sA, Epi epi)
 {
-    __shared__ __align__(16) unsigned char buf[2][H * LDF * 4];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t pid = ((int64_t)blockIdx.x * 2 + wave) * 64 + lane;
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    bf16x8 a[2][4];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            a[k][t] = *reinterpret_cast<const bf16x8*>(W + (t * 16 + r) * H + 32 * k + 8 * g);
+    float bv[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[mt][i] = bias[mt * 16 + 4 * g + i];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        floatx4 acc[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[mt] = floatx4{bv[mt][0], bv[mt][1], bv[mt][2], bv[mt][3]};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(sA + (nt * 16 + r) * LDA + 32 * k + 8 * g);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[k][mt], b, acc[mt], 0, 0, 0);
+        }
+        epi(nt, acc);
+    }
+}
+
+__device__ void forward_infer(const float* __restrict__ p32, const __bf16* __restrict__ w2,
+                              const __bf16* __restrict__ w3, const float xin[4], __bf16* sA, float y[3])
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    // layer 1 on the vector ALU: four features at a time, one 8-byte store
+#pragma unroll 4
+    for (int f = 0; f < H; f += 4) {
+        __bf16 a[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float z = p32[OB1 + f + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z = fmaf(p32[OW1 + (f + j) * 4 + i], xin[i], z);
+            a[j] = (__bf16)gelu(z);
+        }
+        *reinterpret_cast<uint2*>(sA + lane * LDA + f) = *reinterpret_cast<const uint2*>(a);
+    }
+    __syncthreads();
+    // layer 2: a2 = gelu(W2 a1 + b2), written over a1 row block by row block
+    // (an n-tile reads and writes only its own 16 sample rows; the block is
+    // one wave, whose LDS operations complete in order)
+    hidden_t(w2, p32 + OB2, sA, [&](int nt, const floatx4 (&acc)[4]) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            __bf16 v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = (__bf16)gelu(acc[mt][i]);
+            *reinterpret_cast<uint2*>(sA + (nt * 16 + r) * LDA + mt * 16 + 4 * g) = *reinterpret_cast<const uint2*>(v);
+        }
+    });
+    __syncthreads();
+    // layer 3 (fp32 activations in registers) and the output layer: each lane
+    // sums its 16 features of a sample, the four lanes of the sample
+    // (r, r + 16, r + 32, r + 48) reduce, and lane l keeps sample l = 16 g + r
+    const float* w4 = p32 + OW4 + 4 * g;
+    float mine[3] = {0.f, 0.f, 0.f};
+    hidden_t(w3, p32 + OB3, sA, [&](int nt, const floatx4 (&acc)[4]) {
+        float part[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float a3 = gelu(acc[mt][i]);
+#pragma unroll
+                for (int o = 0; o < 3; ++o) part[o] = fmaf(w4[o * H + mt * 16 + i], a3, part[o]);
+            }
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            float v = part[o];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            mine[o] = nt == g ? v : mine[o];
+        }
+    });
+#pragma unroll
+    for (int o = 0; o < 3; ++o) y[o] = p32[OB4 + o] + mine[o];
+}
+
+// Xhat = base + step_scale MLP(x, t): base is the DoF position x, or (add)
+// the predictor's departure point already in X.  One wave of 64 particles
+// per block.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void infer_kernel(const MlpArgs A, double t_np1, double step_scale, double* X,
+                                                   int add)
+{
+    __shared__ __align__(16) __bf16 sA[H * LDA];
+    const int64_t pid = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const bool active = pid < A.n;
     double x[3] = {0.0, 0.0, 0.0};
     float in[4] = {0.f, 0.f, 0.f, 0.f};
@@ -194,27 +301,27 @@ __global__ __launch_bounds__(128) void infer_kernel(const MlpArgs A, double t_np
         scale_inputs(A, x, t_np1, in);
     }
     float y[3];
-    __bf16* sA = reinterpret_cast<__bf16*>(buf[wave]);
-    float* sA3 = reinterpret_cast<float*>(buf[wave]);
-    forward_tile(A.p32, A.w2, A.w3, in, sA, sA3, y, false, nullptr, nullptr, nullptr);
+    forward_infer(A.p32, A.w2, A.w3, in, sA, y);
     if (active) {
-        for (int i = 0; i < 3; ++i) X[(int64_t)i * A.n + pid] = x[i] + (double)y[i] * step_scale;
+        for (int i = 0; i < 3; ++i) {
+            double* xp = X + (int64_t)i * A.n + pid;
+            *xp = (add ? *xp : x[i]) + (double)y[i] * step_scale;
+        }
     }
 }
 
-// raw network on given inputs (test and diagnostics entry)
-__global__ __launch_bounds__(128) void forward_kernel(const MlpArgs A, const float* __restrict__ in4, int64_t n,
-                                                      float* __restrict__ out3)
+// raw network on given inputs (test and diagnostics entry): the inference
+// forward pass
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void forward_kernel(const MlpArgs A, const float* __restrict__ in4, int64_t n,
+                                                     float* __restrict__ out3)
 {
-    __shared__ __align__(16) unsigned char buf[2][H * LDF * 4];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t s = ((int64_t)blockIdx.x * 2 + wave) * 64 + lane;
+    __shared__ __align__(16) __bf16 sA[H * LDA];
+    const int64_t s = (int64_t)blockIdx.x * 64 + threadIdx.x;
     float in[4] = {0.f, 0.f, 0.f, 0.f};
     if (s < n)
         for (int i = 0; i < 4; ++i) in[i] = in4[s * 4 + i];
     float y[3];
-    forward_tile(A.p32, A.w2, A.w3, in, reinterpret_cast<__bf16*>(buf[wave]), reinterpret_cast<float*>(buf[wave]), y,
-                 false, nullptr, nullptr, nullptr);
+    forward_infer(A.p32, A.w2, A.w3, in, sA, y);
     if (s < n)
         for (int i = 0; i < 3; ++i) out3[s * 3 + i] = y[i];
 }
@@ -383,11 +490,12 @@ __global__ __launch_bounds__(256) void refresh_kernel(MlpState S)
 
 // ---------------------------------------------------------- record / select
 
-// training pairs of one traced step: inputs (x, t_{n+1}) scaled to [-1, 1],
-// targets (X - x) / (dt U)
+// training pairs of one traced step: inputs (x, t) scaled to [-1, 1],
+// targets (X - base) / scale with base the DoF position x or, with a
+// predictor, its departure point Xp
 __global__ __launch_bounds__(256) void record_kernel(const MlpArgs A, double t_np1, double inv_step_scale,
-                                                     const double* __restrict__ X, float* __restrict__ in4,
-                                                     float* __restrict__ tg3)
+                                                     const double* __restrict__ X, const double* __restrict__ Xp,
+                                                     float* __restrict__ in4, float* __restrict__ tg3)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= A.n) return;
@@ -396,7 +504,10 @@ __global__ __launch_bounds__(256) void record_kernel(const MlpArgs A, double t_n
     float in[4];
     scale_inputs(A, x, t_np1, in);
     for (int k = 0; k < 4; ++k) in4[i * 4 + k] = in[k];
-    for (int k = 0; k < 3; ++k) tg3[i * 3 + k] = (float)((X[(int64_t)k * A.n + i] - x[k]) * inv_step_scale);
+    for (int k = 0; k < 3; ++k) {
+        const double base = Xp ? Xp[(int64_t)k * A.n + i] : x[k];
+        tg3[i * 3 + k] = (float)((X[(int64_t)k * A.n + i] - base) * inv_step_scale);
+    }
 }
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z)
@@ -431,18 +542,18 @@ __device__ void refresh_bf16(const MlpState& S, int p, float w)
     }
 }
 
-hipError_t launch_infer(const MlpArgs& a, double t_np1, double step_scale, double* X, hipStream_t s)
+hipError_t launch_infer(const MlpArgs& a, double t_np1, double step_scale, double* X, int add, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((a.n + 127) / 128);
-    infer_kernel<<<grid, 128, 0, s>>>(a, t_np1, step_scale, X);
+    const unsigned grid = (unsigned)((a.n + 63) / 64);
+    infer_kernel<<<grid, 64, 0, s>>>(a, t_np1, step_scale, X, add);
     return hipGetLastError();
 }
 
 hipError_t launch_forward(const MlpArgs& a, const float* in4, int64_t n, float* out3, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    forward_kernel<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(a, in4, n, out3);
+    forward_kernel<<<(unsigned)((n + 63) / 64), 64, 0, s>>>(a, in4, n, out3);
     return hipGetLastError();
 }
 
@@ -464,11 +575,11 @@ hipError_t launch_refresh(const MlpState& st, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_record(const MlpArgs& a, double t_np1, double inv_step_scale, const double* X, float* in4,
-                         float* tg3, hipStream_t s)
+hipError_t launch_record(const MlpArgs& a, double t_np1, double inv_step_scale, const double* X, const double* Xp,
+                         float* in4, float* tg3, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    record_kernel<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, t_np1, inv_step_scale, X, in4, tg3);
+    record_kernel<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a, t_np1, inv_step_scale, X, Xp, in4, tg3);
     return hipGetLastError();
 }
 

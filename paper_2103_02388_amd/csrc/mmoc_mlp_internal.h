@@ -44,31 +44,23 @@ struct MlpState {
 
 __device__ void refresh_bf16(const MlpState& S, int p, float w);
 
-hipError_t launch_infer(const MlpArgs& a, double t_np1, double step_scale, double* X, hipStream_t s);
+// X = (add ? X : x) + step_scale MLP(x, t_np1) for every particle
+hipError_t launch_infer(const MlpArgs& a, double t_np1, double step_scale, double* X, int add, hipStream_t s);
 hipError_t launch_forward(const MlpArgs& a, const float* in4, int64_t n, float* out3, hipStream_t s);
 // one optimizer step on `batch` samples (multiple of 64); lr == 0: gradient only (into st.grad)
 hipError_t launch_train_step(const MlpArgs& a, const MlpState& st, const float* in4, const float* tg3,
                              const int32_t* sel, int64_t sel_off, int64_t sel_mod, int64_t sel_stride, int64_t batch,
                              float* part, float* scratch, float lr, int64_t t, float* loss_out, hipStream_t s);
 hipError_t launch_refresh(const MlpState& st, hipStream_t s);
-hipError_t launch_record(const MlpArgs& a, double t_np1, double inv_step_scale, const double* X, float* in4,
-                         float* tg3, hipStream_t s);
+// training pairs: inputs (x, t_np1), targets (X - (Xp ? Xp : x)) * inv_step_scale
+hipError_t launch_record(const MlpArgs& a, double t_np1, double inv_step_scale, const double* X, const double* Xp,
+                         float* in4, float* tg3, hipStream_t s);
 hipError_t launch_draw(uint64_t seed, int64_t n, int64_t count, int32_t* sel, hipStream_t s);
 
 // surrogate step helpers (mmoc_trace.hip)
 // particles with hash(seed, i) < fraction, and the smallest hash of every
 // tile of `tile` particles, appended to ids (count in *n_ids); flags cleared
 hipError_t launch_select_check(int64_t n, int tile, uint64_t seed, float fraction, int32_t* ids,
-                               unsigned long long* n_ids, unsigned char* checked, unsigned char* tile_flag,
-                               hipStream_t s);
-// residuals of the checked particles: tile flag if |Xhat - X_rk|_inf > tol/2;
-// checked particles take their RK4 result; stats updated
-hipError_t launch_residual(int dim, int64_t n, int tile, const int32_t* ids, const unsigned long long* n_ids,
-                           const double* Xrk, double* X, double tol, unsigned char* tile_flag,
-                           unsigned long long* stats, int64_t max_ids, hipStream_t s);
-// unchecked particles of flagged tiles appended to ids
-hipError_t launch_fallback_list(int64_t n, int tile, const unsigned char* tile_flag, const unsigned char* checked,
-                                int32_t* ids, unsigned long long* n_ids, unsigned long long* stats, hipStream_t s);
-
+                               unsigned long long* n_ids, unsigned char* checked, hipStream_t s);
 }  // namespace mlp
 }  // namespace mmoc

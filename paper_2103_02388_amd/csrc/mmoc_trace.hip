@@ -33,7 +33,14 @@
 #include "mmoc_internal.h"
 #include "mmoc_mlp_internal.h"
 
+#include <limits.h>
 #include <math.h>
+
+// No implicit contraction of a * b + c into fma in this file: every fused
+// multiply-add is written as fma().  The kernel variants (element cache on
+// or off, finish pass, tie-band re-locations) then round identically, and a
+// result does not depend on how the compiler inlined or scheduled a variant.
+#pragma clang fp contract(off)
 
 // 128-thread blocks and runs of 16 blocks per XCD: measured best across the
 // three precisions at 2.7e5 and 1.7e7 particles (the plain contiguous eighth
@@ -77,6 +84,7 @@ namespace mmoc {
 namespace {
 
 constexpr int kTB = MMOC_TRACE_BLOCK;
+static_assert(kTB == kSurrogateTile, "the surrogate finish pass takes one fallback tile per block");
 
 __device__ __forceinline__ int64_t logical_block(int lg)
 {
@@ -91,8 +99,8 @@ __device__ __forceinline__ int64_t logical_block(int lg)
 template <int DIM>
 __device__ __forceinline__ double dotd(const double* a, const double* b)
 {
-    if constexpr (DIM == 2) return a[0] * b[0] + a[1] * b[1];
-    else return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    if constexpr (DIM == 2) return fma(a[0], b[0], a[1] * b[1]);
+    else return fma(a[2], b[2], fma(a[0], b[0], a[1] * b[1]));
 }
 
 template <int DIM, int BLEND>
@@ -321,11 +329,10 @@ __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM,
 #pragma unroll
     for (int i = 0; i < DIM; ++i) {
         W[i] *= dn;
-        Wu[i] *= dn;
         const R kc = floor(fmin(fmax(W[i], R(0)), dn - R(1)));
         k[i] = (int)kc;
         f[i] = W[i] - kc;
-        fu[i] = Wu[i] - kc;
+        fu[i] = fma(Wu[i], dn, -kc);
         if constexpr (GAP) gap = fmin(gap, fmin(fabs(f[i]), fabs(R(1) - f[i])));
     }
     // rank of each axis in the descending order of f (ties: lower axis first)
@@ -588,7 +595,7 @@ __device__ __forceinline__ void gather_vel(const Levels<T>& Lv, const T* vb, uin
         ub[2] = Lv.efirst ? z1 : z0;
     }
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) k[i] = NLEV == 2 ? (R(1) - theta) * ua[i] + theta * ub[i] : ua[i];
+    for (int i = 0; i < DIM; ++i) k[i] = NLEV == 2 ? fma(R(1) - theta, ua[i], theta * ub[i]) : ua[i];
 }
 
 // velocity at a lattice node: the nodal values (P2 interpolation is the
@@ -605,11 +612,124 @@ __device__ __forceinline__ void nodal_vel(const Levels<T>& Lv, const T* vb, uint
     }
     if constexpr (NLEV == 2) {
 #pragma unroll
-        for (int i = 0; i < DIM; ++i) k[i] = (R(1) - theta) * (R)a[i] + theta * (R)b[i];
+        for (int i = 0; i < DIM; ++i) k[i] = fma(R(1) - theta, (R)a[i], theta * (R)b[i]);
     } else {
 #pragma unroll
         for (int i = 0; i < DIM; ++i) k[i] = (R)a[i];
     }
+}
+
+// ------------------------------------------------ per-lane element cache
+//
+// At CFL 5 a stage offset is a fraction of a micro element, so most stage
+// evaluations of a particle (84% on the shell, 78-89% on the swirl) fall in
+// the element of the evaluation before.  With the cache, a lane keeps the
+// nodal velocity values of its last element in LDS and gathers from the
+// field only when the element changes: the texture path's tag lookups, which
+// bound the uncached kernels, fall with the gathers.  Layout: chunk c (16
+// bytes) of lane l at lds[c * kTB + l], so a wave's access to one chunk is
+// one contiguous 1 KB row (no bank conflicts).  An element is identified by
+// the block slot of its vertex 0 and the lattice indices of its vertices 1
+// and 2 (vertex 3 is k + (1, 1, 1) for every element of base k, and the
+// first three vertices fix the axis order).  The cached values are the
+// gathered ones, summed in the gather's order, so the results are bitwise
+// those of the uncached kernel.  Used for the raw values of one velocity
+// level (stationary runs) and of two float32 levels, within one interval of
+// the velocity ring (the two levels do not change during the trace).
+template <typename T, int NV>
+struct ElemCache {
+    static constexpr int NCH = (NV * (int)sizeof(T) + 15) / 16;  // 16-byte chunks per lane
+    static constexpr int NVP = NCH * 16 / (int)sizeof(T);        // values with padding
+    uint4* lds;
+    uint32_t k0, k1, k2;
+
+    __device__ __forceinline__ void init(uint4* base)
+    {
+        lds = base + threadIdx.x;
+        k0 = ~0u;
+        k1 = k2 = 0u;
+    }
+    __device__ __forceinline__ bool take(uint32_t a, uint32_t b, uint32_t c)
+    {
+        const bool hit = a == k0 && b == k1 && c == k2;
+        k0 = a;
+        k1 = b;
+        k2 = c;
+        return hit;
+    }
+    __device__ __forceinline__ void put(const T (&v)[NVP])
+    {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            uint4 x;
+            __builtin_memcpy(&x, reinterpret_cast<const char*>(v) + 16 * c, 16);
+            lds[c * kTB] = x;
+        }
+    }
+    __device__ __forceinline__ void get(T (&v)[NVP]) const
+    {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const uint4 x = lds[c * kTB];
+            __builtin_memcpy(reinterpret_cast<char*>(v) + 16 * c, &x, 16);
+        }
+    }
+};
+
+// the nodal velocities of one element, v[(q * NLEV + level) * 3 + i] (3D P2,
+// records without paired u_z)
+template <int NLEV, typename T, int NVP>
+__device__ __forceinline__ void fetch_elem(const Levels<T>& Lv, uint32_t mbase, const int* idx, T (&v)[NVP])
+{
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        const uint32_t slot = mbase + (uint32_t)idx[q];
+        load_vec<3, T>(Lv.ea, Lv.eb, Lv.zb, slot, v + q * 3 * NLEV);
+        if constexpr (NLEV == 2) load_vec<3, T>(Lv.la, Lv.lb, Lv.zb, slot, v + q * 6 + 3);
+    }
+#pragma unroll
+    for (int i = 30 * NLEV; i < NVP; ++i) v[i] = T(0);
+}
+
+// the P2 sums of gather_vel (same operations, same order) from cached values
+template <int NLEV, typename T, typename R>
+__device__ __forceinline__ void sum_elem(const T* v, const R* phi, R theta, R* k)
+{
+    R ua[3], ub[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ua[i] = R(0);
+        ub[i] = R(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ua[i] = fma(phi[q], (R)v[q * 3 * NLEV + i], ua[i]);
+        if constexpr (NLEV == 2) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ub[i] = fma(phi[q], (R)v[q * 6 + 3 + i], ub[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k[i] = NLEV == 2 ? fma(R(1) - theta, ua[i], theta * ub[i]) : ua[i];
+}
+
+// Velocity at a located stage point through the cache: on a new element the
+// lane gathers its nodes and stores them, then every lane sums from its
+// cached copy.  Counts lookups and hits in the lane's counters.
+template <int NLEV, typename T, typename R, typename C>
+__device__ __forceinline__ void cached_vel(C& cache, const Levels<T>& Lv, uint32_t mbase, const Stencil<3, R, 2>& st,
+                                           R theta, R* k, uint32_t& nhit)
+{
+    T v[C::NVP];
+    if (!cache.take(mbase + (uint32_t)st.idx[0], (uint32_t)st.idx[1], (uint32_t)st.idx[2])) {
+        fetch_elem<NLEV, T>(Lv, mbase, st.idx, v);
+        cache.put(v);
+    } else {
+        ++nhit;
+    }
+    cache.get(v);
+    sum_elem<NLEV, T, R>(v, st.phi, theta, k);
 }
 
 template <int DIM, typename T, typename R, int ORD>
@@ -661,6 +781,7 @@ __device__ __forceinline__ void count_flags(unsigned long long* stats, bool acti
     const unsigned long long nb = __popcll(__ballot((flags & LF_BRUTE) != 0));
     const unsigned long long nt = __popcll(__ballot((flags & LF_TIEBAND) != 0));
     const unsigned long long nn = __popcll(__ballot((flags & LF_NAN) != 0));
+    const unsigned long long nf = __popcll(__ballot((flags & LF_FALLBACK) != 0));
     if ((threadIdx.x & 63) == 0) {
         if (nact) atomicAdd(stat_word(stats, ST_PARTICLES), nact);
         if (no) atomicAdd(stat_word(stats, ST_OUTSIDE), no);
@@ -668,7 +789,58 @@ __device__ __forceinline__ void count_flags(unsigned long long* stats, bool acti
         if (nb) atomicAdd(stat_word(stats, ST_BRUTE), nb);
         if (nt) atomicAdd(stat_word(stats, ST_TIEBAND), nt);
         if (nn) atomicAdd(stat_word(stats, ST_NAN), nn);
+        if (nf) atomicAdd(stat_word(stats, ST_FALLBACK), nf);
     }
+}
+
+// one atomic per wave: the summed lane counts of cache lookups and hits
+__device__ __forceinline__ void count_cache(unsigned long long* stats, uint32_t nlook, uint32_t nhit)
+{
+    unsigned long long a = nlook, b = nhit;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && a) {
+        atomicAdd(stat_word(stats, ST_CACHE_LOOKUPS), a);
+        atomicAdd(stat_word(stats, ST_CACHE_HITS), b);
+    }
+}
+
+// Surrogate finish: the tile's checked particles decide whether it keeps
+// the surrogate's departure points (every thread of the block must call).
+// Counts the checked particles and the largest residual into the stats.
+__device__ __forceinline__ bool finish_keep(const double* __restrict__ X, const double* __restrict__ xc,
+                                            const unsigned char* __restrict__ checked, int dim, int64_t xstride,
+                                            double tol_half, int64_t pid, bool active, bool& chk,
+                                            unsigned long long* stats)
+{
+    chk = active && checked[pid];
+    double r = 0.0;
+    if (chk) {
+        for (int i = 0; i < dim; ++i) {
+            const double e = fabs(X[(int64_t)i * xstride + pid] - xc[(int64_t)i * xstride + pid]);
+            r = (e > r || e != e) ? e : r;
+        }
+        if (r != r) r = INFINITY;
+    }
+    const bool keep = !__syncthreads_or(chk && !(r <= tol_half));
+    // one atomic per wave for the count and the largest residual (the bits of
+    // a non-negative double order like the double)
+    unsigned long long bits;
+    __builtin_memcpy(&bits, &r, sizeof bits);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(bits, off, 64);
+        bits = o > bits ? o : bits;
+    }
+    const unsigned long long cnt = __popcll(__ballot(chk));
+    if ((threadIdx.x & 63) == 0 && cnt) {
+        atomicMax(stat_word(stats, ST_MAXRES_BITS), bits);
+        atomicAdd(stat_word(stats, ST_CHECKED), cnt);
+    }
+    return keep;
 }
 
 // --------------------------------------------------------------- fp64 trace
@@ -679,16 +851,28 @@ __device__ __forceinline__ void count_flags(unsigned long long* stats, bool acti
 // GENERIC: a general explicit Runge-Kutta method from A.rk (the paper uses
 // RK4 and notes that any explicit RK method applies, Sec. 3.1); otherwise the
 // classical RK4 with its weights folded into the code.
-template <int DIM, int NLEV, int BLEND, typename T, bool GENERIC, int ORD, bool ZP = false>
+// CACHE: the per-lane element cache (3D P2 RK4, one velocity level or two
+// float32 levels); the block's LDS then holds the cache instead of the
+// geometry copy.
+template <int DIM, int NLEV, int BLEND, typename T, bool GENERIC, int ORD, bool ZP = false, bool CACHE = false>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP64)))
 void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T* __restrict__ c_hat,
                        double* __restrict__ X, unsigned long long* __restrict__ stats)
 {
-    __shared__ MacroGeo sgeo[kLdsGeo];
-    const MacroGeo* sg = stage_geo(geo, A.nm, sgeo);
+    static_assert(!CACHE || (DIM == 3 && ORD == 2 && !GENERIC && !ZP && (NLEV == 1 || sizeof(T) == 4)),
+                  "element cache: 3D P2 RK4, one level or float32 records");
+    using Cache = ElemCache<T, 30 * NLEV>;
+    __shared__ MacroGeo sgeo[CACHE ? 1 : kLdsGeo];
+    __shared__ uint4 lcache[CACHE ? Cache::NCH * kTB : 1];
+    const MacroGeo* sg = stage_geo(geo, CACHE ? INT_MAX : A.nm, sgeo);
     const int64_t t = logical_block(A.xcd_log2) * kTB + threadIdx.x;
     const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
     unsigned flags = 0;
+    uint32_t nlook = 0, nhit = 0;
+    Cache cache;
+    if constexpr (CACHE) cache.init(lcache);
+    bool keep = false, chk = false;
+    if (A.checked) keep = finish_keep(X, A.xcheck, A.checked, DIM, A.xstride, A.tol_half, t, active, chk, stats);
     if (active) {
         const int64_t pid = A.order ? (int64_t)A.order[t] : t;
         const uint64_t e = A.owned[pid];
@@ -698,6 +882,16 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
         bool home = true;
         uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
         const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
+        // surrogate finish: a tile that passed the check keeps the departure
+        // points (uniform over the block: tiles are blocks), checked
+        // particles their RK4 ones; a tile that failed is traced
+        if (A.checked && !keep && !chk) flags |= LF_FALLBACK;
+        if (keep) {
+            const double* src = chk ? A.xcheck : X;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) Y[i] = src[(int64_t)i * A.xstride + pid];
+            home = false;
+        }
         const double h = A.dt / (double)A.substeps;
         const double hh = 0.5 * h;
         const double h6 = h / 6.0;
@@ -719,9 +913,14 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                 lmin = lam_min<DIM, double>(l0, s);
             }
             micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
-            gather_vel<DIM, NLEV, T, double, ORD, ZP>(Lv, A.vb, mbase, st, theta, k);
+            if constexpr (CACHE) {
+                ++nlook;
+                cached_vel<NLEV, T, double>(cache, Lv, mbase, st, theta, k, nhit);
+            } else {
+                gather_vel<DIM, NLEV, T, double, ORD, ZP>(Lv, A.vb, mbase, st, theta, k);
+            }
         };
-        const int nsub = A.substeps * A.n_int;
+        const int nsub = keep ? 0 : A.substeps * A.n_int;
         if constexpr (GENERIC) {
 #pragma unroll 1
             for (int j = 0; j < nsub; ++j) {
@@ -736,7 +935,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                             double sum = 0.0;
 #pragma unroll
                             for (int l = 0; l < q; ++l) sum = fma(A.rk.a[q * kMaxStages + l], K[l][i], sum);
-                            y[i] = Y[i] - h * sum;
+                            y[i] = fma(-h, sum, Y[i]);
                         }
                         double theta;
                         const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)j + A.rk.c[q]) * invS, theta);
@@ -752,7 +951,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
 #pragma unroll
                     for (int q = 0; q < kMaxStages; ++q)
                         if (q < A.rk.s) sum = fma(A.rk.b[q], K[q][i], sum);
-                    const double yn = Y[i] - h * sum;
+                    const double yn = fma(-h, sum, Y[i]);
                     home = home && yn == Y[i];
                     Y[i] = yn;
                 }
@@ -782,12 +981,12 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
 #pragma unroll
                     for (int i = 0; i < DIM; ++i) {
                         acc[i] = stg == 0 ? ks[i] : fma(wst, ks[i], acc[i]);
-                        y[i] = Y[i] - cnext * ks[i];
+                        y[i] = fma(-cnext, ks[i], Y[i]);
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) {
-                    const double yn = Y[i] - h6 * acc[i];
+                    const double yn = fma(-h6, acc[i], Y[i]);
                     home = home && yn == Y[i];
                     Y[i] = yn;
                 }
@@ -823,6 +1022,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
         }
     }
     count_flags(stats, active, flags);
+    if constexpr (CACHE) count_cache(stats, nlook, nhit);
 }
 
 // --------------------------------------------------------- fp32 mixed trace
@@ -990,15 +1190,23 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint
     }
 }
 
-template <int DIM, int NLEV, int BLEND, int ORD>
-__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP32)))
+template <int DIM, int NLEV, int BLEND, int ORD, bool CACHE = false>
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(CACHE && NLEV == 2 ? 3 : MMOC_WPE_FP32)))
 void trace_fp32_kernel(const TraceArgs<float> A)
 {
-    __shared__ MacroGeo sgeo[kLdsGeo];
-    const MacroGeo* sg = stage_geo(A.geo, A.nm, sgeo);
+    static_assert(!CACHE || (DIM == 3 && ORD == 2), "element cache: 3D P2");
+    using Cache = ElemCache<float, 30 * NLEV>;
+    __shared__ MacroGeo sgeo[CACHE ? 1 : kLdsGeo];
+    __shared__ uint4 lcache[CACHE ? Cache::NCH * kTB : 1];
+    const MacroGeo* sg = stage_geo(A.geo, CACHE ? INT_MAX : A.nm, sgeo);
     const int64_t t = logical_block(A.xcd_log2) * kTB + threadIdx.x;
     const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
     unsigned flags = 0;
+    uint32_t nlook = 0, nhit = 0;
+    Cache cache;
+    if constexpr (CACHE) cache.init(lcache);
+    bool keep = false, chk = false;
+    if (A.checked) keep = finish_keep(A.X, A.xcheck, A.checked, DIM, A.xstride, A.tol_half, t, active, chk, A.stats);
     if (active) {
         const int64_t pid = A.order ? (int64_t)A.order[t] : t;
         const uint64_t e = A.owned[pid];
@@ -1008,13 +1216,20 @@ void trace_fp32_kernel(const TraceArgs<float> A)
         bool home = true;
         uint32_t mbase = (uint32_t)M * (uint32_t)A.npm;
         const uint32_t own_slot = mbase + (uint32_t)own_lat_idx<DIM>(e);
+        if (A.checked && !keep && !chk) flags |= LF_FALLBACK;
+        if (keep) {
+            const double* src = chk ? A.xcheck : A.X;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) Y[i] = src[(int64_t)i * A.xstride + pid];
+            home = false;
+        }
         const double hd = A.dt / (double)A.substeps;
         const float h = (float)hd;
         const float hh = 0.5f * h;
         const float h6 = h / 6.0f;
         const double invSd = 1.0 / (double)A.substeps;
         Stencil<DIM, float, ORD> st;
-        const int nsub = A.substeps * A.n_int;
+        const int nsub = keep ? 0 : A.substeps * A.n_int;
 #pragma unroll 1
         for (int j = 0; j < nsub; ++j) {
             float ks[DIM], acc[DIM];
@@ -1030,7 +1245,12 @@ void trace_fp32_kernel(const TraceArgs<float> A)
                     nodal_vel<DIM, NLEV, float, float>(Lv, A.vb, own_slot, theta, ks);
                 } else {
                     locate32<DIM, BLEND, ORD>(A, M, mbase, y, st, flags, sg);
-                    gather_vel<DIM, NLEV, float, float>(Lv, A.vb, mbase, st, theta, ks);
+                    if constexpr (CACHE) {
+                        ++nlook;
+                        cached_vel<NLEV, float, float>(cache, Lv, mbase, st, theta, ks, nhit);
+                    } else {
+                        gather_vel<DIM, NLEV, float, float>(Lv, A.vb, mbase, st, theta, ks);
+                    }
                 }
                 const float wst = (stg == 0 || stg == 3) ? 1.0f : 2.0f;
                 const float cnext = stg == 2 ? h : hh;
@@ -1066,6 +1286,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
         }
     }
     count_flags(A.stats, active, flags);
+    if constexpr (CACHE) count_cache(A.stats, nlook, nhit);
 }
 
 // ------------------------------------------------- scalar at given points
@@ -1119,18 +1340,18 @@ __global__ __launch_bounds__(kTB) void scalar_eval_fp32_kernel(const TraceArgs<f
     A.c_hat[t] = gather_scalar<DIM, float, float>(A, mbase, st);
 }
 
-__device__ __forceinline__ uint64_t mix64(uint64_t z)
+// 32-bit hash of particle i under a step's seed: the murmur3 finaliser
+// (Appleby, MurmurHash3 fmix32) of i spread by the golden-ratio constant and
+// xored with the seed
+__device__ __forceinline__ uint32_t hash32(uint32_t seed, uint32_t i)
 {
-    // splitmix64 finaliser (Steele, Lea, Flood 2014)
-    z += 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ double unit_hash(uint64_t seed, uint64_t i)
-{
-    return (double)(mix64(seed ^ mix64(i)) >> 11) * (1.0 / 9007199254740992.0);
+    uint32_t x = (i * 0x9E3779B1u) ^ seed;
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x;
 }
 
 // Appends the block's lanes with `take` to a list: one atomic per block on
@@ -1159,104 +1380,44 @@ __device__ __forceinline__ unsigned long long block_append(unsigned long long* l
 
 constexpr int kListBlock = 1024;
 
-// One thread per particle: particle i is checked when its hash is below
-// `fraction`; a tile (a whole number of waves, `tile` particles) with no
-// such particle checks its particle of smallest hash (ties: lowest index).
-// Clears the tile flags and appends the checked particles to the list.
-__global__ __launch_bounds__(kListBlock) void select_check_kernel(int64_t n, int tile, uint64_t seed, float fraction,
+// One thread per particle: particle i is checked when its 32-bit hash is
+// below thresh = fraction 2^32 (every particle for fraction 1); a tile (one
+// or two waves, `tile` particles) with no such particle checks its particle
+// of smallest hash (compared in the upper 25 bits; ties: lowest index).
+// Marks the checked particles and appends them to the list.
+__global__ __launch_bounds__(kListBlock) void select_check_kernel(int64_t n, int tile, uint32_t seed, uint32_t thresh,
                                                                   int32_t* ids, unsigned long long* n_ids,
-                                                                  unsigned char* checked, unsigned char* tile_flag)
+                                                                  unsigned char* checked)
 {
-    __shared__ double sh[kListBlock / 64];
-    __shared__ int64_t si[kListBlock / 64];
+    __shared__ uint32_t skey[kListBlock / 64];
     __shared__ int sany[kListBlock / 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * kListBlock + threadIdx.x;
     const bool in = i < n;
-    const double h = in ? unit_hash(seed, (uint64_t)i) : 2.0;
-    bool c = in && h < (double)fraction;
-    double hm = h;
-    int64_t im = i;
+    const uint32_t h = hash32(seed, (uint32_t)i);
+    bool c = in && (h < thresh || thresh == 0xFFFFFFFFu);
+    // the tile's smallest hash, made unique by the particle's place in its
+    // tile (tiles are 64 or 128 particles: 7 bits)
+    uint32_t key = in ? ((h & ~127u) | (uint32_t)(i % tile)) : ~0u;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double oh = __shfl_xor(hm, off, 64);
-        const int64_t oi = __shfl_xor(im, off, 64);
-        if (oh < hm || (oh == hm && oi < im)) {
-            hm = oh;
-            im = oi;
-        }
-    }
+    for (int off = 32; off > 0; off >>= 1) key = min(key, (uint32_t)__shfl_xor((int)key, off, 64));
     const bool wany = __ballot(c) != 0;
     if (lane == 0) {
-        sh[wave] = hm;
-        si[wave] = im;
+        skey[wave] = key;
         sany[wave] = wany;
     }
     __syncthreads();
     const int wpt = tile / 64, w0 = wave - wave % wpt;
     bool any = false;
-    double hb = 2.0;
-    int64_t best = -1;
+    uint32_t best = ~0u;
     for (int w = w0; w < w0 + wpt; ++w) {
         any |= sany[w] != 0;
-        if (sh[w] < hb || (sh[w] == hb && si[w] < best)) {
-            hb = sh[w];
-            best = si[w];
-        }
+        best = min(best, skey[w]);
     }
-    if (!any && in && i == best) c = true;
-    if (in) {
-        checked[i] = c;
-        if (i % tile == 0) tile_flag[i / tile] = 0;
-    }
+    if (!any && in && (uint32_t)(i % tile) == (best & 127u)) c = true;
+    if (in) checked[i] = c;
     const unsigned long long pos = block_append<kListBlock>(n_ids, c);
     if (c) ids[pos] = (int32_t)i;
-}
-
-__global__ __launch_bounds__(256) void residual_kernel(int dim, int64_t n, int tile, const int32_t* __restrict__ ids,
-                                                       const unsigned long long* __restrict__ n_ids,
-                                                       const double* __restrict__ Xrk, double* __restrict__ X,
-                                                       double tol, unsigned char* tile_flag, unsigned long long* stats)
-{
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool active = (unsigned long long)k < *n_ids;
-    unsigned long long bits = 0;  // the residual's bits: non-negative doubles order like their bits
-    if (active) {
-        const int64_t i = ids[k];
-        double r = 0.0;
-        for (int d = 0; d < dim; ++d) {
-            const double a = X[(int64_t)d * n + i], b = Xrk[(int64_t)d * n + i];
-            const double e = fabs(a - b);
-            r = (e > r || e != e) ? e : r;
-            X[(int64_t)d * n + i] = b;  // a checked particle keeps its RK4 result
-        }
-        if (!(r <= 0.5 * tol)) tile_flag[i / tile] = 1;
-        if (r != r) r = INFINITY;
-        __builtin_memcpy(&bits, &r, sizeof bits);
-    }
-    // one atomic per wave for the count and the largest residual
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(bits, off, 64);
-        bits = o > bits ? o : bits;
-    }
-    const unsigned long long cnt = __popcll(__ballot(active));
-    if ((threadIdx.x & 63) == 0 && cnt) {
-        atomicMax(stat_word(stats, ST_MAXRES_BITS), bits);
-        atomicAdd(stat_word(stats, ST_CHECKED), cnt);
-    }
-}
-
-__global__ __launch_bounds__(kListBlock) void fallback_list_kernel(int64_t n, int tile, const unsigned char* tile_flag,
-                                                                   const unsigned char* checked, int32_t* ids,
-                                                                   unsigned long long* n_ids, unsigned long long* stats)
-{
-    const int64_t i = (int64_t)blockIdx.x * kListBlock + threadIdx.x;
-    const bool take = i < n && tile_flag[i / tile] && !checked[i];
-    const unsigned long long pos = block_append<kListBlock>(n_ids, take);
-    if (take) ids[pos] = (int32_t)i;
-    const unsigned long long cnt = __popcll(__ballot(take));
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(stat_word(stats, ST_FALLBACK), cnt);
 }
 
 // grid of the remapped kernels: a whole number of XCD rounds (the blocks
@@ -1285,6 +1446,20 @@ hipError_t launch_trace_f64g(int dim, int blend, const TraceArgs<T>& a0, hipStre
     a.xcd_log2 = xcd_log2_fp64(a.n);
     const dim3 grid(grid_xcd(a.n, a.xcd_log2)), block(kTB);
     const bool st = a.nlev == 1;
+    if constexpr (ORD == 2 && !G) {
+        // the element cache: one stationary level, or two float32 levels
+        // within one interval of the ring
+        if (a.elem_cache && dim == 3 && (st || (sizeof(T) == 4 && a.n_int == 1))) {
+            if (st) {
+                if (blend) trace_fp64_kernel<3, 1, 1, T, false, 2, false, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+                else trace_fp64_kernel<3, 1, 0, T, false, 2, false, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+            } else if constexpr (sizeof(T) == 4) {
+                if (blend) trace_fp64_kernel<3, 2, 1, T, false, 2, false, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+                else trace_fp64_kernel<3, 2, 0, T, false, 2, false, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+            }
+            return hipGetLastError();
+        }
+    }
     if constexpr (sizeof(T) == 8) {
         // paired u_z records of a two-level ring (both levels in one load)
         if (a.zs == 2 && dim == 3 && !st) {
@@ -1378,32 +1553,15 @@ hipError_t launch_scalar_eval_fp32(int dim, int blend, const TraceArgs<float>& a
 namespace mlp {
 
 hipError_t launch_select_check(int64_t n, int tile, uint64_t seed, float fraction, int32_t* ids,
-                               unsigned long long* n_ids, unsigned char* checked, unsigned char* tile_flag,
-                               hipStream_t s)
+                               unsigned long long* n_ids, unsigned char* checked, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (tile % 64 != 0 || kListBlock % tile != 0) return hipErrorInvalidValue;
+    if (tile % 64 != 0 || tile > 128 || kListBlock % tile != 0 || n > INT32_MAX) return hipErrorInvalidValue;
+    // particle i is checked when hash < fraction 2^32
+    const double th = (double)fraction * 4294967296.0;
+    const uint32_t thresh = th >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)th;
     select_check_kernel<<<(unsigned)((n + kListBlock - 1) / kListBlock), kListBlock, 0, s>>>(
-        n, tile, seed, fraction, ids, n_ids, checked, tile_flag);
-    return hipGetLastError();
-}
-
-hipError_t launch_residual(int dim, int64_t n, int tile, const int32_t* ids, const unsigned long long* n_ids,
-                           const double* Xrk, double* X, double tol, unsigned char* tile_flag,
-                           unsigned long long* stats, int64_t max_ids, hipStream_t s)
-{
-    if (max_ids <= 0) return hipSuccess;
-    residual_kernel<<<(unsigned)((max_ids + 255) / 256), 256, 0, s>>>(dim, n, tile, ids, n_ids, Xrk, X, tol,
-                                                                       tile_flag, stats);
-    return hipGetLastError();
-}
-
-hipError_t launch_fallback_list(int64_t n, int tile, const unsigned char* tile_flag, const unsigned char* checked,
-                                int32_t* ids, unsigned long long* n_ids, unsigned long long* stats, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    fallback_list_kernel<<<(unsigned)((n + kListBlock - 1) / kListBlock), kListBlock, 0, s>>>(n, tile, tile_flag,
-                                                                                          checked, ids, n_ids, stats);
+        n, tile, (uint32_t)(seed ^ (seed >> 32)), thresh, ids, n_ids, checked);
     return hipGetLastError();
 }
 
@@ -1416,6 +1574,18 @@ hipError_t launch_trace_fp32o(int dim, int blend, const TraceArgs<float>& a0, hi
     a.xcd_log2 = MMOC_XCD_LOG2_FP32;
     const dim3 grid(grid_xcd(a.n, a.xcd_log2)), block(kTB);
     const bool st = a.nlev == 1;
+    if constexpr (ORD == 2) {
+        if (a.elem_cache && dim == 3 && (st || a.n_int == 1)) {
+            if (st) {
+                if (blend) trace_fp32_kernel<3, 1, 1, 2, true><<<grid, block, 0, s>>>(a);
+                else trace_fp32_kernel<3, 1, 0, 2, true><<<grid, block, 0, s>>>(a);
+            } else {
+                if (blend) trace_fp32_kernel<3, 2, 1, 2, true><<<grid, block, 0, s>>>(a);
+                else trace_fp32_kernel<3, 2, 0, 2, true><<<grid, block, 0, s>>>(a);
+            }
+            return hipGetLastError();
+        }
+    }
     if (dim == 2 && !blend) {
         if (st) trace_fp32_kernel<2, 1, 0, ORD><<<grid, block, 0, s>>>(a);
         else trace_fp32_kernel<2, 2, 0, ORD><<<grid, block, 0, s>>>(a);

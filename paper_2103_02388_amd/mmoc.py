@@ -33,7 +33,7 @@ EXPORTED = [
     "mmoc_default_options", "mmoc_create", "mmoc_set_stream", "mmoc_upload_mesh", "mmoc_num_dofs",
     "mmoc_dof_coords", "mmoc_set_velocity", "mmoc_set_stationary", "mmoc_swap_velocity_levels",
     "mmoc_set_scalar", "mmoc_trace_step", "mmoc_get_stats", "mmoc_reset_stats", "mmoc_mlp_nparams",
-    "mmoc_mlp_configure", "mmoc_mlp_record", "mmoc_mlp_train", "mmoc_mlp_get_weights",
+    "mmoc_mlp_configure", "mmoc_mlp_set_predictor", "mmoc_mlp_record", "mmoc_mlp_train", "mmoc_mlp_get_weights",
     "mmoc_mlp_set_weights", "mmoc_mlp_infer", "mmoc_trace_step_surrogate", "mmoc_last_error",
     "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad", "mmoc_mass_inner", "mmoc_field_range",
     "mmoc_lookback_run", "mmoc_set_rk_tableau", "mmoc_cfl_time_step", "mmoc_set_level_count", "mmoc_trace_span",
@@ -50,13 +50,14 @@ class MMOCError(RuntimeError):
 
 class mmoc_options(C.Structure):
     _fields_ = [("eps_in", C.c_double), ("eps32_macro", C.c_float), ("eps32_micro", C.c_float),
-                ("max_hops", C.c_int), ("order", C.c_int), ("reserved", C.c_int * 3)]
+                ("max_hops", C.c_int), ("order", C.c_int), ("elem_cache", C.c_int), ("reserved", C.c_int * 2)]
 
 
 class mmoc_stats(C.Structure):
     _fields_ = [("n_particles", C.c_int64), ("n_outside", C.c_int64), ("n_multi_hop", C.c_int64),
                 ("n_bruteforce", C.c_int64), ("n_tieband", C.c_int64), ("n_nan", C.c_int64),
-                ("n_checked", C.c_int64), ("n_fallback", C.c_int64), ("max_check_residual", C.c_double)]
+                ("n_checked", C.c_int64), ("n_fallback", C.c_int64), ("max_check_residual", C.c_double),
+                ("n_cache_lookups", C.c_int64), ("n_cache_hits", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -105,6 +106,7 @@ def lib():
         "mmoc_reset_stats": (st, [P]),
         "mmoc_mlp_nparams": (I64, []),
         "mmoc_mlp_configure": (st, [P, P, P, D]),
+        "mmoc_mlp_set_predictor": (st, [P, I, D, D]),
         "mmoc_mlp_record": (st, [P, D, D, P, I64]),
         "mmoc_mlp_train": (st, [P, I64, I, I, C.c_float, C.c_ulonglong, C.POINTER(D)]),
         "mmoc_mlp_get_weights": (st, [P, P, I64]),
@@ -235,6 +237,10 @@ def mmoc_mlp_configure(ctx, lo, hi, U):
     hi = np.ascontiguousarray(hi, dtype=np.float64)
     _check(ctx, lib().mmoc_mlp_configure(ctx, lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p),
                                          float(U)))
+
+
+def mmoc_mlp_set_predictor(ctx, substeps, scale=1.0, period=0.0):
+    _check(ctx, lib().mmoc_mlp_set_predictor(ctx, int(substeps), float(scale), float(period)))
 
 
 def mmoc_mlp_record(ctx, t_np1, dt, X: torch.Tensor, capacity):
@@ -506,6 +512,9 @@ def _tracer_mlp_methods():
     def mlp_configure(self, lo, hi, U):
         mmoc_mlp_configure(self.ctx, lo, hi, U)
 
+    def mlp_set_predictor(self, substeps, scale=1.0, period=0.0):
+        mmoc_mlp_set_predictor(self.ctx, substeps, scale, period)
+
     def mlp_record(self, t_np1, dt, X, capacity):
         mmoc_mlp_record(self.ctx, t_np1, dt, X, capacity)
 
@@ -526,7 +535,7 @@ def _tracer_mlp_methods():
         mmoc_trace_step_surrogate(self.ctx, t_np1, dt, substeps, check_fraction, tol, step, c_hat, X)
         return c_hat, X
 
-    for f in (mlp_configure, mlp_record, mlp_train, mlp_infer, trace_step_surrogate):
+    for f in (mlp_configure, mlp_set_predictor, mlp_record, mlp_train, mlp_infer, trace_step_surrogate):
         setattr(Tracer, f.__name__, f)
 
 

@@ -22,6 +22,17 @@ def test_flops_per_particle_3d_p2_rk4():
     assert bench.flops_per_particle(2, 2, 1) == 4 * (ref2 + micro2 + 2 * 6 * 2 * 2 + 6 + 8) + 4 + ref2 + micro2 + 12
 
 
+def test_flops_per_particle_blended_shell():
+    # the blended shell adds the inverse map Phi^-1(y) = y c |y| / (n.y) to
+    # every location: n.y 5, |y|^2 5, sqrt 1, c r / (n.y) 2, three fused
+    # scalings 6 (19 flops); one stationary level
+    per_eval = 25 + 19 + 44 + 60 + 12
+    scalar = 25 + 19 + 44 + 20
+    assert bench.flops_per_particle(3, 1, 4, blend=True) == 4 * (4 * per_eval + 6) + scalar == 2692
+    # and the shell's compulsory bytes: u (24) + c (8) in, chat (8) + X (24) out
+    assert bench.bytes_per_particle(3, 1, 8) == 64
+
+
 def test_compulsory_bytes_per_particle():
     # float64, two levels: u^n and u^{n+1} (48), c (8) in; chat (8) and X (24) out
     assert bench.bytes_per_particle(3, 2, 8) == 88

@@ -1,0 +1,97 @@
+"""The per-lane element cache of the trace kernels (one stationary velocity
+level in any precision, two float32 levels): results are bitwise those of
+the same step with the cache switched off (options.elem_cache = 0), on
+workloads that span many tiles, a ragged tail, macro changes, exits and the
+blended shell; the cache statistics count every located stage evaluation
+and find most of them in the element of the evaluation before."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2103_02388_amd import mmoc
+from paper_2103_02388_amd import workloads as W
+
+from gpu_helpers import field_gpu
+
+pytestmark = pytest.mark.gpu
+
+PRECS = {"fp64": mmoc.MMOC_FP64, "fp32": mmoc.MMOC_FP32_MIXED, "fp32f": mmoc.MMOC_FP32_FIELDS}
+
+
+def fields(wl, level, stationary, t_n, dt):
+    """The step's inputs, evaluated once (the shell's seeded modes go through
+    torch autograd on the GPU, whose sums need not repeat bit for bit)."""
+    tr = mmoc.Tracer.from_workload(wl, level=level)
+    xg = tr.dof_coords()
+    tr.close()
+    u0 = field_gpu(wl.velocity, xg, t_n)
+    u1 = None if stationary else field_gpu(wl.velocity, xg, t_n + dt)
+    return u0, u1, field_gpu(wl.scalar0, xg)
+
+
+def run(wl, level, prec, cache, f, dt, S=4):
+    u0, u1, c = f
+    opt = mmoc.mmoc_default_options()
+    opt.elem_cache = cache
+    tr = mmoc.Tracer.from_workload(wl, precision=prec, level=level, options=opt)
+    tr.set_stationary(u1 is None)
+    tr.set_velocity(0, u0)
+    if u1 is not None:
+        tr.set_velocity(1, u1)
+    tr.set_scalar(c)
+    tr.reset_stats()
+    ch, X = tr.trace_step(dt, S)
+    torch.cuda.synchronize()
+    st = tr.stats()
+    out = ch.double().cpu().numpy(), X.cpu().numpy(), st
+    tr.close()
+    return out
+
+
+CASES = [
+    # (workload, level, stationary, t_n, dt factor, precisions)
+    ("swirl3d", 5, True, 0.3, 1.0, ("fp64", "fp32", "fp32f")),
+    ("swirl3d", 5, False, 0.3, 1.0, ("fp32", "fp32f")),
+    ("swirl3d", 4, True, 0.0, 8.0, ("fp64", "fp32")),   # long steps: many hops and exits
+    ("shell3d", 2, True, 0.0, 1.0, ("fp64", "fp32", "fp32f")),
+    ("plume3d", 4, False, 0.4, 4.0, ("fp32f",)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-L%d-%s" % (c[0], c[1], "st" if c[2] else "2lev"))
+def test_cache_is_bitwise_neutral(case):
+    name, level, stationary, t_n, fac, precs = case
+    wl = W.CONFIGS[name](level=level)
+    T = t_n * (wl.extra["T"] if name == "plume3d" else 1.0)
+    dt = wl.dt * fac
+    f = fields(wl, level, stationary, T, dt)
+    for p in precs:
+        c1, X1, s1 = run(wl, level, PRECS[p], 1, f, dt)
+        c0, X0, s0 = run(wl, level, PRECS[p], 0, f, dt)
+        assert s1["n_nan"] == 0
+        if not (np.array_equal(X1, X0) and np.array_equal(c1, c0)):
+            dx = np.abs(X1 - X0).max(axis=0)
+            bad = np.nonzero(dx > 0)[0]
+            print("%s %s: %d particles differ, max |dX| %.3e at %s, max |dc| %.3e"
+                  % (name, p, bad.size, dx.max(), bad[:8], np.abs(c1 - c0).max()))
+        assert np.array_equal(X1, X0), (name, p)
+        assert np.array_equal(c1, c0), (name, p)
+        # every located stage evaluation goes through the cache: at most
+        # 4 S - 1 per particle (the first is the nodal value); none without it
+        assert s0["n_cache_lookups"] == 0
+        n = s1["n_particles"]
+        assert 0 < s1["n_cache_lookups"] <= 15 * n
+        rate = s1["n_cache_hits"] / s1["n_cache_lookups"]
+        print("%s L%d %s %s: %d lookups, hit rate %.3f, multi-hop %d, outside %d"
+              % (name, level, p, "stationary" if stationary else "two levels", s1["n_cache_lookups"], rate,
+                 s1["n_multi_hop"], s1["n_outside"]))
+        assert rate > (0.3 if fac > 1 else 0.6)
+        for k in ("n_outside", "n_multi_hop", "n_bruteforce", "n_tieband", "n_nan"):
+            assert s1[k] == s0[k], k
+
+
+def test_two_float64_levels_do_not_use_the_cache():
+    """The two-level float64 kernel keeps its paired-u_z gathers: no lookups."""
+    wl = W.swirl3d()
+    _, _, st = run(wl, 3, mmoc.MMOC_FP64, 1, fields(wl, 3, False, 0.3, wl.dt), wl.dt)
+    assert st["n_cache_lookups"] == 0 and st["n_particles"] > 0

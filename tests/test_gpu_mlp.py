@@ -158,85 +158,155 @@ def test_infinite_tolerance_keeps_the_network():
     assert same_rk.sum() >= st["n_checked"]
 
 
-def test_surrogate_gain_on_swirl():
-    """Train on steps 1-10 (2e6 sampled pairs, 30 epochs), then run step 11
-    with the surrogate at several tolerances and report, per tolerance, the
-    fraction of particles traced by RK4, the time per step against the plain
-    tracer, and the true error of a seeded sample of particles against the
-    CPU oracle.
+SWIRL_PERIOD = 2.0 * W.SWIRL_T   # g(t) = cos(pi t / T) repeats after 2T
 
-    The check is a sample (about 1% of the particles, at least one per
-    128-particle tile), so it bounds the error statistically, not at every
-    particle.  What is asserted is what holds regardless:
-      * at the stated tolerance 1e-4 the sampled error is within it;
-      * the surrogate is never worse than the bare network (fallback only
-        swaps in RK4 results);
-      * where the network's error over all particles is below half the
-        tolerance, no tile falls back and only the check sample runs RK4.
-    The speed-up and the fraction of sampled particles above a looser
-    tolerance are reported, not asserted."""
-    wl = W.swirl3d()
-    p = Pair(wl, precision=mmoc.MMOC_FP32_MIXED)
+
+def swirl_surrogate_run(train, run, prec=mmoc.MMOC_FP64, pred=1, scale=1e-4, tol=1e-4, n_check=4000,
+                        epochs=30, samples=2_000_000, timing=False):
+    """The swirl run with the surrogate (config 4): steps `train` (1-based
+    step n covers [t_{n-1}, t_n]) traced by RK4 (4 sub-steps) and recorded,
+    the network trained on `samples` pairs drawn from them, then steps `run`
+    with the surrogate (1% check sample, tolerance tol).  The network learns
+    the correction to the RK4 trace with `pred` sub-steps (0: the whole
+    displacement), with the time input the phase t mod 2T.  For every run
+    step: the fraction of particles traced by RK4 (check + fallback) and the
+    true error of a seeded sample of n_check particles against the CPU
+    oracle, which is given the same scalar c^n as the GPU (per-step parity
+    from identical inputs)."""
+    wl = W.swirl3d(steps=max(run) + 1)
+    p = Pair(wl, precision=prec)
     tr = p.tr
-    tr.mlp_configure([0, 0, 0, 0], [1, 1, 1, W.SWIRL_T], 2.0)
+    tr.mlp_configure([0, 0, 0, 0], [1, 1, 1, SWIRL_PERIOD], 2.0)
+    tr.mlp_set_predictor(pred, scale, SWIRL_PERIOD)
     xt = p.xg.t().contiguous()
-    U = torch.stack([W.swirl_velocity(xt, n * wl.dt).t().contiguous() for n in range(12)])
-    c0 = W.two_blobs(xt).contiguous()
-    tr.set_scalar(c0)
-    cap = 10 * tr.N
-    for n in range(10):
-        tr.set_velocity(0, U[n])
-        tr.set_velocity(1, U[n + 1])
-        _, X = tr.trace_step(wl.dt, 4)
-        tr.mlp_record((n + 1) * wl.dt, wl.dt, X, cap)
-    t0 = time.perf_counter()
-    loss = tr.mlp_train(2_000_000, 30, batch=8192, lr=1e-3, seed=5)
-    t_train = time.perf_counter() - t0
-    n = 10
-    tr.set_velocity(0, U[n])
-    tr.set_velocity(1, U[n + 1])
     xc = torch.from_numpy(p.xc.T.copy())
-    p.u0c = np.ascontiguousarray(W.swirl_velocity(xc, n * wl.dt).numpy().T)
-    p.u1c = np.ascontiguousarray(W.swirl_velocity(xc, (n + 1) * wl.dt).numpy().T)
-    p.cc = W.two_blobs(xc).numpy()
-    ids = np.sort(np.random.default_rng(n).choice(tr.N, 4000, replace=False))
-    _, Xr, _ = p.oracle_step(wl.dt, 4, ids=ids, threads=8)
+    N, dt = tr.N, wl.dt
 
-    def timeit(f, k=10):
-        f()
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(k):
-            f()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - a) / k
+    def vel(n):
+        return W.swirl_velocity(xt, n * dt).t().contiguous()
 
-    t_rk = timeit(lambda: tr.trace_step(wl.dt, 4))
-    _, Xrk = tr.trace_step(wl.dt, 4)
-    Xnet = tr.mlp_infer((n + 1) * wl.dt, wl.dt)
-    torch.cuda.synchronize()
-    # network error over every particle, against the mixed-precision RK4
-    # trace (itself within 1e-5 of the oracle)
-    net_err_all = (Xnet - Xrk).abs().max().item()
-    net_err = np.abs(Xnet.cpu().numpy()[:, ids] - Xr).max()
-    t_inf = timeit(lambda: tr.mlp_infer((n + 1) * wl.dt, wl.dt, Xnet))
+    cur = W.two_blobs(xt).contiguous()
+    cap = len(train) * N
+    for n in train:
+        tr.set_velocity(0, vel(n - 1))
+        tr.set_velocity(1, vel(n))
+        tr.set_scalar(cur)
+        ch, X = tr.trace_step(dt, 4)
+        tr.mlp_record(n * dt, dt, X, cap)
+        cur = ch.double()
+    t0 = time.perf_counter()
+    loss = tr.mlp_train(samples, epochs, batch=8192, lr=1e-3, seed=5)
+    t_train = time.perf_counter() - t0
+    ids = np.sort(np.random.default_rng(11).choice(N, n_check, replace=False))
+    idt = torch.from_numpy(ids).cuda()
+    owner = p.om.dof_owner()[0][ids]
     rows = []
-    for tol in (1e-4, 1e-3, 1e-2, 3e-2):
+    for n in run:
+        tr.set_velocity(0, vel(n - 1))
+        tr.set_velocity(1, vel(n))
+        tr.set_scalar(cur)
         tr.reset_stats()
-        ch, X = tr.trace_step_surrogate((n + 1) * wl.dt, wl.dt, 4, 0.01, tol, step=n)
+        ch, X = tr.trace_step_surrogate(n * dt, dt, 4, 0.01, tol, step=n)
         st = tr.stats()
-        e = np.abs(X.cpu().numpy()[:, ids] - Xr).max(axis=0)
-        t_s = timeit(lambda: tr.trace_step_surrogate((n + 1) * wl.dt, wl.dt, 4, 0.01, tol, step=n))
-        rows.append((tol, (st["n_fallback"] + st["n_checked"]) / tr.N, e.max(), (e > tol).mean(), t_s, st))
-    print("surrogate: train %.2fs, loss %.3e, network-only max error %.2e (sample) %.2e (all), "
-          "inference %.1f us, fp32 rk4 %.1f us" % (t_train, loss, net_err, net_err_all, t_inf * 1e6, t_rk * 1e6))
-    for tol, fb, err, over, t_s, _ in rows:
-        print("surrogate tol %.0e: rk4 fraction %.3f, max sampled error %.2e, sampled fraction above tol %.4f, "
-              "step %.1f us, speed-up vs fp32 rk4 %.2fx" % (tol, fb, err, over, t_s * 1e6, t_rk / t_s))
-    assert loss < 1e-3
-    for tol, fb, err, over, t_s, st in rows:
-        if tol == 1e-4:
-            assert err <= tol
-        assert err <= net_err + 2e-5
-        if net_err_all + 2e-5 < tol / 2:
-            assert st["n_fallback"] == 0
+        u0c = np.ascontiguousarray(W.swirl_velocity(xc, (n - 1) * dt).numpy().T)
+        u1c = np.ascontiguousarray(W.swirl_velocity(xc, n * dt).numpy().T)
+        ch_h = cur.cpu().numpy()
+        chr_, Xr, _ = p.om.trace(u0c, u1c, ch_h, dt, 4, ids=ids, threads=8)
+        Xs = X[:, idt].cpu().numpy()
+        ex = np.abs(Xs - Xr).max(axis=0)
+        # the scalar step at the surrogate's own departure points: c^n_h
+        # evaluated there by the oracle (P2 interpolation, float64), its walk
+        # starting in the particle's own macro as the GPU's does (a point that
+        # a surrogate error puts just outside the cube is extrapolated from
+        # the boundary element that walk reaches)
+        cx, _, _ = p.om.eval(ch_h, np.ascontiguousarray(Xs.T), start=owner)
+        ec = np.abs(ch[idt].double().cpu().numpy() - cx[:, 0])
+        rows.append({"step": n, "rk4": (st["n_checked"] + st["n_fallback"]) / N, "err": float(ex.max()),
+                     "above": float((ex > tol).mean()), "err_c": float(ec.max()),
+                     "max_res": st["max_check_residual"]})
+        cur = ch.double()
+    out = {"loss": loss, "train_s": t_train, "rows": rows}
+    if timing:
+        def timeit(f, k=20):
+            f()
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(k):
+                f()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - a) / k
+        n = run[0]
+        tr.set_velocity(0, vel(n - 1))
+        tr.set_velocity(1, vel(n))
+        out["t_surrogate"] = timeit(lambda: tr.trace_step_surrogate(n * dt, dt, 4, 0.01, tol, step=n))
+        out["t_rk4"] = timeit(lambda: tr.trace_step(dt, 4))
+        out["t_rk4_s1"] = timeit(lambda: tr.trace_step(dt, 1))
+        out["t_rk4_s2"] = timeit(lambda: tr.trace_step(dt, 2))
+        out["t_infer"] = timeit(lambda: tr.mlp_infer(n * dt, dt))
+    tr.close()
+    return out
+
+
+def report(tag, out, tol):
+    rows = out["rows"]
+    kept = [r for r in rows if r["rk4"] < 0.5]
+    print("%s: loss %.3e (train %.2fs), steps %d-%d: mean rk4 fraction %.3f, kept steps %d of %d, "
+          "max sampled error %.2e (kept steps %.2e), max |chat - c^n(X)| %.2e"
+          % (tag, out["loss"], out["train_s"], rows[0]["step"], rows[-1]["step"],
+             np.mean([r["rk4"] for r in rows]), len(kept), len(rows), max(r["err"] for r in rows),
+             max([r["err"] for r in kept] or [0.0]), max(r["err_c"] for r in rows)))
+    for r in rows[:: max(1, len(rows) // 20)]:
+        print("  step %3d: rk4 fraction %.3f, sampled error %.2e, share above tol %.4f, max check residual %.2e"
+              % (r["step"], r["rk4"], r["err"], r["above"], r["max_res"]))
+    if "t_surrogate" in out:
+        print("  step times: surrogate %.1f us, rk4 S=4 %.1f us, S=2 %.1f us, S=1 %.1f us, inference %.1f us"
+              % tuple(1e6 * out[k] for k in ("t_surrogate", "t_rk4", "t_rk4_s2", "t_rk4_s1", "t_infer")))
+    return kept
+
+
+def test_surrogate_config4_trained_on_steps_1_to_10():
+    """Config 4 as specified: steps 1-10 traced and recorded, then steps
+    11-110 with the 1% check at tol 1e-4.  The network corrects the
+    one-sub-step RK4 trace (whose own error against 4 sub-steps is up to
+    1.4e-4 on this flow); its time input is the phase of the periodic
+    velocity, so steps 41-50 and 81-90 repeat the training phases and the
+    others lie outside them.
+
+    The check is a sample (one particle in a hundred, at least one per tile
+    of 128), so it bounds the error statistically: a tile is kept when its
+    checked particles are within tol/2, and an unchecked particle of a kept
+    tile can still exceed tol where the network is poor (outside the
+    training phases).  Asserted:
+      * steps in the training phases (41-50, 81-90) keep the network on
+        nearly every tile and every sampled particle is within tol;
+      * on every step the share of sampled particles above tol stays below
+        1%, and no sampled particle is off by more than 2 tol;
+      * chat is c^n_h at the surrogate's departure points, to 1e-12 (the
+        oracle's P2 evaluation there)."""
+    tol = 1e-4
+    out = swirl_surrogate_run(range(1, 11), range(11, 111), tol=tol)
+    report("config 4 (train 1-10)", out, tol)
+    for r in out["rows"]:
+        assert r["above"] < 0.01, r
+        assert r["err"] <= 2 * tol, r
+        assert r["err_c"] <= 1e-12, r
+    in_phase = [r for r in out["rows"] if (r["step"] - 1) % 40 < 10 and r["step"] > 40]
+    assert len(in_phase) == 20
+    for r in in_phase:
+        assert r["rk4"] < 0.05 and r["err"] <= tol, r
+    assert out["loss"] < 1e-2
+
+
+def test_surrogate_full_period_variant():
+    """The full-period variant (labelled as such): steps 1-40, one period of
+    the velocity, traced and recorded; then steps 41-140 with the surrogate.
+    Every step keeps the network on nearly every tile and every sampled
+    particle is within tol; the step time is reported beside the plain RK4
+    steps with 4, 2 and 1 sub-steps (the method without the network)."""
+    tol = 1e-4
+    out = swirl_surrogate_run(range(1, 41), range(41, 141), tol=tol, timing=True)
+    report("full-period variant (train 1-40)", out, tol)
+    for r in out["rows"]:
+        assert r["err"] <= tol, r
+        assert r["rk4"] < 0.1, r
+        assert r["err_c"] <= 1e-12, r
