@@ -241,6 +241,22 @@ mmoc_status mmoc_cfl_time_step(mmoc_ctx* ctx, double cfl, int level, double* tau
 mmoc_status mmoc_mass_inner(mmoc_ctx* ctx, const double* a_dev, const double* a_sub_dev, const double* b_dev,
                             const double* b_sub_dev, double* out);
 
+/* mmoc_mass_inner for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, bit for bit, but the
+ * partial sums live in a file-scope device array of the library (512 KiB per
+ * GPU, held until the process ends) and the result goes to out_dev, one
+ * float64 of caller-owned device memory.  Asynchronous on the context's
+ * stream; allocates nothing, copies nothing to the host and does not
+ * synchronise.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other contexts, other host threads)
+ * race.  Errors: MMOC_E_UNSUPPORTED on blended meshes (their mass matrix is
+ * the assembled one); MMOC_E_ARG for a mesh needing more than 65,536
+ * partial sums (one per 256 micro cubes: the 6-tetrahedron cube up to level
+ * 7) or bad buffers; MMOC_E_STATE before a mesh is uploaded. */
+mmoc_status mmoc_mass_inner_noalloc(mmoc_ctx* ctx, const double* a_dev, const double* a_sub_dev,
+                                    const double* b_dev, const double* b_sub_dev, double* out_dev);
+
 /* Smallest and largest nodal value of a unique-layout [n_unique] float64
  * device array (var = max - min and the peak ratio of Sec. 3.1); NaNs are
  * skipped.  Synchronises the stream. */

@@ -49,6 +49,7 @@ struct mmoc_ctx {
     mmoc::RKTab rk{};         // general explicit RK tableau (s == 0: classical RK4)
     double* red_d = nullptr;  // partial sums of the metric reductions, red_cap doubles
     int64_t red_cap = 0;
+    double* noalloc_d = nullptr;  // this device's allocation-free scratch (not owned)
 
     std::vector<mmoc::MacroGeo> geo_h;  // host copy of the geometry table
 

@@ -235,6 +235,11 @@ mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec,
         delete c;
         return MMOC_E_HIP;
     }
+    // the allocation-free entry points' scratch array on this device
+    if (mmoc::noalloc_scratch(c->device, &c->noalloc_d) != hipSuccess) {
+        (void)hipGetLastError();
+        c->noalloc_d = nullptr;
+    }
     if (dev_alloc(c, &c->stats_d, (size_t)mmoc::ST_COUNT * mmoc::kStatSpread, "stats") != MMOC_OK ||
         hipMemset(c->stats_d, 0, sizeof(unsigned long long) * mmoc::ST_COUNT * mmoc::kStatSpread) != hipSuccess) {
         free_all(c);

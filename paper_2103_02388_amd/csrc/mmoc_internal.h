@@ -167,6 +167,11 @@ struct MassRef {
 };
 // blocks (partial sums) of one a^T M b launch
 int64_t mass_inner_blocks(int dim, int nm, int n);
+// The allocation-free mass inner product keeps its partial sums in a
+// file-scope device array of this many doubles (512 KiB per GPU).
+constexpr int64_t kNoAllocPartials = (int64_t)1 << 16;
+// device address of that array on `device` (the current device)
+hipError_t noalloc_scratch(int device, double** out);
 // out[0] = (a - a_sub)^T M (b - b_sub) over the whole refined mesh (a null:
 // ones; a_sub, b_sub null: zero); partial holds mass_inner_blocks doubles
 hipError_t launch_mass_inner(int dim, int ord, const MacroGeo* geo, const int32_t* slot_uid, int64_t npm, int nm,

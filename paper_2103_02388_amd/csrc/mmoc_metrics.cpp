@@ -126,6 +126,38 @@ mmoc_status mmoc_mass_inner(mmoc_ctx* c, const double* a, const double* a_sub, c
     return MMOC_OK;
 }
 
+mmoc_status mmoc_mass_inner_noalloc(mmoc_ctx* c, const double* a, const double* a_sub, const double* b,
+                                    const double* b_sub, double* out_dev)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (c->blend)
+        return fail(c, MMOC_E_UNSUPPORTED, "blended meshes use the assembled mass matrix (mmoc_mass_inner)");
+    const size_t bytes = sizeof(double) * (size_t)c->N;
+    const double* ptrs[4] = {a, a_sub, b, b_sub};
+    const char* names[4] = {"a_dev", "a_sub_dev", "b_dev", "b_sub_dev"};
+    mmoc_status st;
+    for (int i = 0; i < 4; ++i)
+        if (ptrs[i] && (st = check_dev(c, ptrs[i], bytes, 8, names[i])) != MMOC_OK) return st;
+    if ((st = check_dev(c, out_dev, sizeof(double), 8, "out_dev")) != MMOC_OK) return st;
+    const int64_t nb = mmoc::mass_inner_blocks(c->dim, c->nm, c->n);
+    if (nb > mmoc::kNoAllocPartials)
+        return fail(c, MMOC_E_ARG,
+                    "mesh too large for the allocation-free path: %lld partial sums, at most %lld (use mmoc_mass_inner)",
+                    (long long)nb, (long long)mmoc::kNoAllocPartials);
+    if (!c->noalloc_d) return fail(c, MMOC_E_STATE, "the device scratch array has no address on this device");
+    static const mmoc::MassRef R2 = mass_unit(2, 2), R3 = mass_unit(3, 2), Q2 = mass_unit(2, 1),
+                               Q3 = mass_unit(3, 1);
+    const int ord = c->opt.order;
+    const mmoc::MassRef& R = ord == 2 ? (c->dim == 3 ? R3 : R2) : (c->dim == 3 ? Q3 : Q2);
+    // every block writes its own partial sum: nothing in the array needs clearing
+    HIPCHK(c,
+           mmoc::launch_mass_inner(c->dim, ord, c->geo_d, c->slot_uid_d, c->npm, c->nm, c->n, R, a, a_sub, b, b_sub,
+                                   c->noalloc_d, out_dev, c->stream),
+           "mass inner product");
+    return MMOC_OK;
+}
+
 mmoc_status mmoc_field_range(mmoc_ctx* c, const double* cf, double* min_out, double* max_out)
 {
     if (!c || !min_out || !max_out) return MMOC_E_ARG;

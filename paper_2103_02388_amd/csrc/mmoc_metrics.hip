@@ -15,6 +15,15 @@
 
 #include <math.h>
 
+#include <mutex>
+
+// Partial sums of the allocation-free mass inner product
+// (mmoc_mass_inner_noalloc): one array per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel (in host code it
+// is a stand-in, not a device address): it uses the device address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+static __device__ __align__(256) double scratch[mmoc::kNoAllocPartials];
+
 namespace mmoc {
 namespace {
 
@@ -304,6 +313,25 @@ hipError_t launch_range(const double* c, int64_t n, double* partial, int64_t nbl
     if (e != hipSuccess) return e;
     range_final_kernel<<<1, 64, 0, s>>>(partial, partial + nblocks, nblocks, out);
     return hipGetLastError();
+}
+
+// Device address of `scratch` on `device`, which must be the current
+// device: taken once per device with hipGetSymbolAddress and kept.
+hipError_t noalloc_scratch(int device, double** out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double*>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace mmoc

@@ -35,7 +35,7 @@ EXPORTED = [
     "mmoc_set_scalar", "mmoc_trace_step", "mmoc_get_stats", "mmoc_reset_stats", "mmoc_mlp_nparams",
     "mmoc_mlp_configure", "mmoc_mlp_set_predictor", "mmoc_mlp_record", "mmoc_mlp_train", "mmoc_mlp_get_weights",
     "mmoc_mlp_set_weights", "mmoc_mlp_infer", "mmoc_trace_step_surrogate", "mmoc_last_error",
-    "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad", "mmoc_mass_inner", "mmoc_field_range",
+    "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad", "mmoc_mass_inner", "mmoc_mass_inner_noalloc", "mmoc_field_range",
     "mmoc_lookback_run", "mmoc_set_rk_tableau", "mmoc_cfl_time_step", "mmoc_set_level_count", "mmoc_trace_span",
     "mmoc_fe_assemble", "mmoc_fe_export", "mmoc_fe_apply", "mmoc_boundary_mask", "mmoc_diffusion_step",
     "mmoc_set_fields",
@@ -116,6 +116,7 @@ def lib():
         "mmoc_mlp_loss_grad": (st, [P, P, P, I64, P, C.POINTER(D)]),
         "mmoc_trace_step_surrogate": (st, [P, D, D, I, C.c_float, D, I64, P, P]),
         "mmoc_mass_inner": (st, [P, P, P, P, P, C.POINTER(D)]),
+        "mmoc_mass_inner_noalloc": (st, [P, P, P, P, P, P]),
         "mmoc_field_range": (st, [P, P, C.POINTER(D), C.POINTER(D)]),
         "mmoc_lookback_run": (st, [P, D, I, I64, I64, P, I64, P]),
         "mmoc_set_rk_tableau": (st, [P, I, P, P, P]),
@@ -291,6 +292,12 @@ def mmoc_mass_inner(ctx, a, a_sub, b, b_sub):
     out = C.c_double()
     _check(ctx, lib().mmoc_mass_inner(ctx, _ptr(a), _ptr(a_sub), _ptr(b), _ptr(b_sub), C.byref(out)))
     return out.value
+
+
+def mmoc_mass_inner_noalloc(ctx, a, a_sub, b, b_sub, out: torch.Tensor):
+    """(a - a_sub)^T M (b - b_sub) into out (one float64 on the device),
+    asynchronously, with no device allocation."""
+    _check(ctx, lib().mmoc_mass_inner_noalloc(ctx, _ptr(a), _ptr(a_sub), _ptr(b), _ptr(b_sub), _ptr(out)))
 
 
 def mmoc_field_range(ctx, c):
