@@ -581,6 +581,12 @@ def time_surrogate(S, swirl):
     pl = W.plume3d()
     out["plume3d_config5"] = surrogate_run(pl, pl.velocity, range(1, 11), range(11, 201), pl.extra["T"],
                                            pl.extra["umax"], 0.0, S=S)
+    # the same with float32 records (predictor, check and fallback through
+    # the element cache), against the float32-fields and float64 RK4 steps
+    f = surrogate_run(pl, pl.velocity, range(1, 11), range(11, 201), pl.extra["T"], pl.extra["umax"], 0.0, S=S,
+                      prec_name="fp32f")
+    f["speedup_vs_fp64_rk4"] = out["plume3d_config5"]["rk4_ms"] / f["surrogate_ms"]
+    out["plume3d_config5_fp32_fields"] = f
     return out
 
 

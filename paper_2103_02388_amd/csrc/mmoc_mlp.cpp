@@ -3,6 +3,7 @@
 // surrogate step (inference, RK4 check sample, per-tile fallback).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -449,11 +450,18 @@ mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* c, double t_np1, double dt, int 
     // 1. the seeded check sample (at least one per tile), then RK4 on it
     HIPCHK(c, hipMemsetAsync(S->n_ids, 0, sizeof(unsigned long long), S->aux), "clear count");
     const uint64_t seed = 0x243F6A8885A308D3ull ^ ((uint64_t)step * 0x9E3779B97F4A7C15ull);
-    HIPCHK(c, launch_select_check(N, kTile, seed, check_fraction, S->ids, S->n_ids, S->checked, S->aux),
+    // The list holds up to `cap` particles: twice the expected share plus one
+    // per tile, so that the check trace launches a grid of that size
+    // instead of one over all particles (a launch of mostly empty blocks
+    // costs as much as the check itself at 1.7e7 particles).  A selection
+    // beyond it is not traced and sends its tile to the fallback.
+    const int64_t cap = std::min<int64_t>(
+        N, 2 * (int64_t)std::ceil((double)check_fraction * (double)N) + (N + kTile - 1) / kTile + 1024);
+    HIPCHK(c, launch_select_check(N, kTile, seed, check_fraction, S->ids, S->n_ids, cap, S->checked, S->aux),
            "check sample");
     TraceExtra on_aux;
     on_aux.stream = S->aux;
-    if ((st = mmoc_launch_trace(c, dt, substeps, nullptr, S->Xrk, S->ids, N, S->n_ids, 0, 1, &on_aux)) != MMOC_OK)
+    if ((st = mmoc_launch_trace(c, dt, substeps, nullptr, S->Xrk, S->ids, cap, S->n_ids, 0, 1, &on_aux)) != MMOC_OK)
         return st;
     HIPCHK(c, hipEventRecord(S->ev_join, S->aux), "join");
     // 2. the surrogate's departure points for every particle: the network

@@ -61,6 +61,6 @@ hipError_t launch_draw(uint64_t seed, int64_t n, int64_t count, int32_t* sel, hi
 // particles with hash(seed, i) < fraction, and the smallest hash of every
 // tile of `tile` particles, appended to ids (count in *n_ids); flags cleared
 hipError_t launch_select_check(int64_t n, int tile, uint64_t seed, float fraction, int32_t* ids,
-                               unsigned long long* n_ids, unsigned char* checked, hipStream_t s);
+                               unsigned long long* n_ids, int64_t cap, unsigned char* checked, hipStream_t s);
 }  // namespace mlp
 }  // namespace mmoc

@@ -286,10 +286,72 @@ struct Stencil {
     static constexpr int NN = ORD == 2 ? (DIM + 1) * (DIM + 2) / 2 : DIM + 1;
     int idx[NN];  // lattice index of the nodes
     R phi[NN];    // shape function values
+    int k[3];     // the element: base cell k and the rank of each axis
+    int r[3];     //   (filled by micro whether or not idx is)
 };
 
 __device__ __forceinline__ int tri_n(int x) { return (x * (x + 1)) >> 1; }
 __device__ __forceinline__ int tet_n(int x) { return (x * (x + 1) * (x + 2)) / 6; }
+
+// Lattice indices of an element's nodes from its base cell k and axis
+// ranks r: micro vertex a is V_a = k + [r < a] (componentwise); P1 nodes
+// are the vertices on the lattice of resolution n, P2 node (a, b) sits at
+// V_a + V_b on the lattice of resolution 2n (vertex nodes a = b first,
+// then the edges a < b).
+template <int DIM, int ORD>
+__device__ __forceinline__ void stencil_idx(const int* k, const int* r, int* idx)
+{
+    if constexpr (ORD == 1) {
+        const int I0 = k[0], J0 = k[1], K0 = k[2];
+        const int TI0 = DIM == 3 ? tet_n(I0) : tri_n(I0);
+        const int TI1 = TI0 + (DIM == 3 ? tri_n(I0 + 1) : I0 + 1);
+        const int TJ0 = DIM == 3 ? tri_n(J0) : J0;
+        const int TJ1 = TJ0 + (DIM == 3 ? J0 + 1 : 1);
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a) {
+            int id = ((r[0] < a) ? TI1 : TI0) + ((r[1] < a) ? TJ1 : TJ0);
+            if constexpr (DIM == 3) id += K0 + (r[2] < a);
+            idx[a] = id;
+        }
+    } else {
+        // 2k + delta with delta_i = [r_i < a] + [r_i < b] in {0,1,2}
+        const int I0 = 2 * k[0], J0 = 2 * k[1], K0 = 2 * k[2];
+        int TI[3], TJ[3];
+        if constexpr (DIM == 3) {
+            TI[0] = tet_n(I0);
+            TI[1] = TI[0] + tri_n(I0 + 1);
+            TI[2] = TI[1] + tri_n(I0 + 2);
+            TJ[0] = tri_n(J0);
+            TJ[1] = TJ[0] + J0 + 1;
+            TJ[2] = TJ[1] + J0 + 2;
+        } else {
+            TI[0] = tri_n(I0);
+            TI[1] = TI[0] + I0 + 1;
+            TI[2] = TI[1] + I0 + 2;
+            TJ[0] = J0;
+            TJ[1] = J0 + 1;
+            TJ[2] = J0 + 2;
+        }
+        auto node = [&](int a, int b) {
+            const int dI = (r[0] < a) + (r[0] < b);
+            const int dJ = (r[1] < a) + (r[1] < b);
+            if constexpr (DIM == 3) {
+                const int dK = (r[2] < a) + (r[2] < b);
+                return (dI == 0 ? TI[0] : (dI == 1 ? TI[1] : TI[2])) + (dJ == 0 ? TJ[0] : (dJ == 1 ? TJ[1] : TJ[2])) +
+                       K0 + dK;
+            } else {
+                return (dI == 0 ? TI[0] : (dI == 1 ? TI[1] : TI[2])) + (dJ == 0 ? TJ[0] : (dJ == 1 ? TJ[1] : TJ[2]));
+            }
+        };
+        int c = 0;
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a) idx[c++] = node(a, a);
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a)
+#pragma unroll
+            for (int b = a + 1; b <= DIM; ++b) idx[c++] = node(a, b);
+    }
+}
 
 // O(1) micro location in the Freudenthal lattice of the macro's Kuhn
 // coordinates w (w_d = s_d, w_a = s_a + w_{a+1}), then the P2 shape
@@ -299,7 +361,7 @@ __device__ __forceinline__ int tet_n(int x) { return (x * (x + 1) * (x + 2)) / 6
 // distance of the selection coordinates W = n w from a tie (an integer, or
 // another coordinate), which the mixed-precision path compares with its
 // micro band (1 without GAP).
-template <int DIM, typename R, bool GAP = false, int ORD = 2>
+template <int DIM, typename R, bool GAP = false, int ORD = 2, bool IDX = true>
 __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM, R, ORD>& st)
 {
     R ssel[DIM];
@@ -358,58 +420,23 @@ __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM,
 #pragma unroll
     for (int a = 1; a < DIM; ++a) mu[a] = g[a - 1] - g[a];
     mu[DIM] = g[DIM - 1];
-    // micro vertex a = k + sum of the first a axes in rank order, i.e.
-    // V_a[i] = k_i + [r_i < a]
-    if constexpr (ORD == 1) {
-        // P1: the nodes are the vertices, on the lattice of resolution n
-        const int I0 = k[0], J0 = k[1], K0 = k[2];
-        const int TI0 = DIM == 3 ? tet_n(I0) : tri_n(I0);
-        const int TI1 = TI0 + (DIM == 3 ? tri_n(I0 + 1) : I0 + 1);
-        const int TJ0 = DIM == 3 ? tri_n(J0) : J0;
-        const int TJ1 = TJ0 + (DIM == 3 ? J0 + 1 : 1);
+    // the element (micro vertex a = k + the first a axes in rank order),
+    // its node indices unless the caller takes them later (IDX false), and
+    // the shape functions at the point
 #pragma unroll
-        for (int a = 0; a <= DIM; ++a) {
-            int id = ((r[0] < a) ? TI1 : TI0) + ((r[1] < a) ? TJ1 : TJ0);
-            if constexpr (DIM == 3) id += K0 + (r[2] < a);
-            st.idx[a] = id;
-            st.phi[a] = mu[a];
-        }
+    for (int i = 0; i < 3; ++i) {
+        st.k[i] = k[i];
+        st.r[i] = r[i];
+    }
+    if constexpr (IDX) stencil_idx<DIM, ORD>(k, r, st.idx);
+    if constexpr (ORD == 1) {
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a) st.phi[a] = mu[a];
         return gap;
     }
-    // P2: node (a,b) sits at V_a + V_b in the lattice of resolution 2n,
-    // 2k + delta with delta_i = [r_i < a] + [r_i < b] in {0,1,2}
-    const int I0 = 2 * k[0], J0 = 2 * k[1], K0 = 2 * k[2];
-    int TI[3], TJ[3];
-    if constexpr (DIM == 3) {
-        TI[0] = tet_n(I0);
-        TI[1] = TI[0] + tri_n(I0 + 1);
-        TI[2] = TI[1] + tri_n(I0 + 2);
-        TJ[0] = tri_n(J0);
-        TJ[1] = TJ[0] + J0 + 1;
-        TJ[2] = TJ[1] + J0 + 2;
-    } else {
-        TI[0] = tri_n(I0);
-        TI[1] = TI[0] + I0 + 1;
-        TI[2] = TI[1] + I0 + 2;
-        TJ[0] = J0;
-        TJ[1] = J0 + 1;
-        TJ[2] = J0 + 2;
-    }
-    auto node = [&](int a, int b) {
-        const int dI = (r[0] < a) + (r[0] < b);
-        const int dJ = (r[1] < a) + (r[1] < b);
-        if constexpr (DIM == 3) {
-            const int dK = (r[2] < a) + (r[2] < b);
-            return (dI == 0 ? TI[0] : (dI == 1 ? TI[1] : TI[2])) + (dJ == 0 ? TJ[0] : (dJ == 1 ? TJ[1] : TJ[2])) +
-                   K0 + dK;
-        } else {
-            return (dI == 0 ? TI[0] : (dI == 1 ? TI[1] : TI[2])) + (dJ == 0 ? TJ[0] : (dJ == 1 ? TJ[1] : TJ[2]));
-        }
-    };
     int c = 0;
 #pragma unroll
     for (int a = 0; a <= DIM; ++a) {
-        st.idx[c] = node(a, a);
         st.phi[c] = mu[a] * fma(R(2), mu[a], R(-1));
         ++c;
     }
@@ -417,7 +444,6 @@ __device__ __forceinline__ R micro(const R* s, R l0, R lmin, int n, Stencil<DIM,
     for (int a = 0; a <= DIM; ++a)
 #pragma unroll
         for (int b = a + 1; b <= DIM; ++b) {
-            st.idx[c] = node(a, b);
             st.phi[c] = R(4) * mu[a] * mu[b];
             ++c;
         }
@@ -641,20 +667,25 @@ struct ElemCache {
     static constexpr int NCH = (NV * (int)sizeof(T) + 15) / 16;  // 16-byte chunks per lane
     static constexpr int NVP = NCH * 16 / (int)sizeof(T);        // values with padding
     uint4* lds;
-    uint32_t k0, k1, k2;
+    uint64_t key;
 
     __device__ __forceinline__ void init(uint4* base)
     {
         lds = base + threadIdx.x;
-        k0 = ~0u;
-        k1 = k2 = 0u;
+        key = ~0ull;
     }
-    __device__ __forceinline__ bool take(uint32_t a, uint32_t b, uint32_t c)
+    // the element's key: its macro's slot base, base cell and axis ranks
+    // (ranks r0, r1 fix r2); 9 bits per cell coordinate cover level 9
+    static __device__ __forceinline__ uint64_t key_of(uint32_t mbase, const int* k, const int* r)
     {
-        const bool hit = a == k0 && b == k1 && c == k2;
-        k0 = a;
-        k1 = b;
-        k2 = c;
+        const uint32_t lo = ((uint32_t)k[0] << 22) | ((uint32_t)k[1] << 13) | ((uint32_t)k[2] << 4) |
+                            (uint32_t)(r[0] * 3 + r[1]);
+        return ((uint64_t)mbase << 32) | lo;
+    }
+    __device__ __forceinline__ bool take(uint64_t k)
+    {
+        const bool hit = k == key;
+        key = k;
         return hit;
     }
     __device__ __forceinline__ void put(const T (&v)[NVP])
@@ -677,7 +708,7 @@ struct ElemCache {
 };
 
 // the nodal velocities of one element, v[(q * NLEV + level) * 3 + i] (3D P2,
-// records without paired u_z)
+// records without paired u_z; idx: the element's node indices)
 template <int NLEV, typename T, int NVP>
 __device__ __forceinline__ void fetch_elem(const Levels<T>& Lv, uint32_t mbase, const int* idx, T (&v)[NVP])
 {
@@ -715,15 +746,18 @@ __device__ __forceinline__ void sum_elem(const T* v, const R* phi, R theta, R* k
 }
 
 // Velocity at a located stage point through the cache: on a new element the
-// lane gathers its nodes and stores them, then every lane sums from its
-// cached copy.  Counts lookups and hits in the lane's counters.
+// lane computes its node indices (the stencil comes without them), gathers
+// the nodes and stores them; then every lane sums from its cached copy.
+// Counts the lane's hits.
 template <int NLEV, typename T, typename R, typename C>
 __device__ __forceinline__ void cached_vel(C& cache, const Levels<T>& Lv, uint32_t mbase, const Stencil<3, R, 2>& st,
                                            R theta, R* k, uint32_t& nhit)
 {
     T v[C::NVP];
-    if (!cache.take(mbase + (uint32_t)st.idx[0], (uint32_t)st.idx[1], (uint32_t)st.idx[2])) {
-        fetch_elem<NLEV, T>(Lv, mbase, st.idx, v);
+    if (!cache.take(C::key_of(mbase, st.k, st.r))) {
+        int idx[10];
+        stencil_idx<3, 2>(st.k, st.r, idx);
+        fetch_elem<NLEV, T>(Lv, mbase, idx, v);
         cache.put(v);
     } else {
         ++nhit;
@@ -816,8 +850,9 @@ __device__ __forceinline__ bool finish_keep(const double* __restrict__ X, const 
                                             double tol_half, int64_t pid, bool active, bool& chk,
                                             unsigned long long* stats)
 {
-    chk = active && checked[pid];
-    double r = 0.0;
+    const unsigned char cv = active ? checked[pid] : 0;
+    chk = cv == 1;
+    double r = cv == 2 ? (double)INFINITY : 0.0;  // selected but not traced: the tile falls back
     if (chk) {
         for (int i = 0; i < dim; ++i) {
             const double e = fabs(X[(int64_t)i * xstride + pid] - xc[(int64_t)i * xstride + pid]);
@@ -825,7 +860,7 @@ __device__ __forceinline__ bool finish_keep(const double* __restrict__ X, const 
         }
         if (r != r) r = INFINITY;
     }
-    const bool keep = !__syncthreads_or(chk && !(r <= tol_half));
+    const bool keep = !__syncthreads_or(cv != 0 && !(r <= tol_half));
     // one atomic per wave for the count and the largest residual (the bits of
     // a non-negative double order like the double)
     unsigned long long bits;
@@ -912,7 +947,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                 l0 = ref_at<DIM, BLEND>(geo, M, y, s, sg);
                 lmin = lam_min<DIM, double>(l0, s);
             }
-            micro<DIM, double, false, ORD>(s, l0, lmin, A.level_n, st);
+            micro<DIM, double, false, ORD, !CACHE>(s, l0, lmin, A.level_n, st);
             if constexpr (CACHE) {
                 ++nlook;
                 cached_vel<NLEV, T, double>(cache, Lv, mbase, st, theta, k, nhit);
@@ -1124,6 +1159,11 @@ __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int 
         out->idx[q] = st.idx[q];
         out->phi[q] = (float)st.phi[q];
     }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        out->k[i] = st.k[i];
+        out->r[i] = st.r[i];
+    }
     return r;
 }
 
@@ -1133,7 +1173,7 @@ __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int 
 // in float64, and so is a micro decision within eps32_micro * n of a tie.
 // Near a boundary face there is no second macro to choose: the point stays,
 // and its element is selected from the clamped barycentrics as in float64.
-template <int DIM, int BLEND, int ORD>
+template <int DIM, int BLEND, int ORD, bool IDX = true>
 __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint32_t& mbase, const double* y,
                                          Stencil<DIM, float, ORD>& st, unsigned& flags, const MacroGeo* sg = nullptr)
 {
@@ -1165,17 +1205,17 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint
             float sf[DIM];
 #pragma unroll
             for (int i = 0; i < DIM; ++i) sf[i] = (float)s64[i];
-            micro<DIM, float, false, ORD>(sf, (float)l064, (float)lmin64, A.level_n, st);
+            micro<DIM, float, false, ORD, IDX>(sf, (float)l064, (float)lmin64, A.level_n, st);
             return;
         }
     }
     bool redo = macro_redo;
     if (!macro_redo) {
         if (A.eps32_micro > 0.0f) {
-            const float gap = micro<DIM, float, true, ORD>(s, l0, lmin, A.level_n, st);
+            const float gap = micro<DIM, float, true, ORD, IDX>(s, l0, lmin, A.level_n, st);
             redo = gap < A.eps32_micro * (float)A.level_n;
         } else {
-            micro<DIM, float, false, ORD>(s, l0, lmin, A.level_n, st);
+            micro<DIM, float, false, ORD, IDX>(s, l0, lmin, A.level_n, st);
         }
     }
     if (redo) {
@@ -1244,7 +1284,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
                 if ((j == 0 && stg == 0) || (home && same_point<DIM>(y, Y))) {
                     nodal_vel<DIM, NLEV, float, float>(Lv, A.vb, own_slot, theta, ks);
                 } else {
-                    locate32<DIM, BLEND, ORD>(A, M, mbase, y, st, flags, sg);
+                    locate32<DIM, BLEND, ORD, !CACHE>(A, M, mbase, y, st, flags, sg);
                     if constexpr (CACHE) {
                         ++nlook;
                         cached_vel<NLEV, float, float>(cache, Lv, mbase, st, theta, ks, nhit);
@@ -1384,10 +1424,11 @@ constexpr int kListBlock = 1024;
 // below thresh = fraction 2^32 (every particle for fraction 1); a tile (one
 // or two waves, `tile` particles) with no such particle checks its particle
 // of smallest hash (compared in the upper 25 bits; ties: lowest index).
-// Marks the checked particles and appends them to the list.
+// Appends the selected particles to the list, up to `cap` entries, and
+// marks them in `checked` (1: in the list, 2: beyond the capacity).
 __global__ __launch_bounds__(kListBlock) void select_check_kernel(int64_t n, int tile, uint32_t seed, uint32_t thresh,
                                                                   int32_t* ids, unsigned long long* n_ids,
-                                                                  unsigned char* checked)
+                                                                  unsigned long long cap, unsigned char* checked)
 {
     __shared__ uint32_t skey[kListBlock / 64];
     __shared__ int sany[kListBlock / 64];
@@ -1415,9 +1456,11 @@ __global__ __launch_bounds__(kListBlock) void select_check_kernel(int64_t n, int
         best = min(best, skey[w]);
     }
     if (!any && in && (uint32_t)(i % tile) == (best & 127u)) c = true;
-    if (in) checked[i] = c;
     const unsigned long long pos = block_append<kListBlock>(n_ids, c);
-    if (c) ids[pos] = (int32_t)i;
+    // a selected particle beyond the list's capacity is marked 2 (selected,
+    // not traced): the finish pass sends its tile to the fallback
+    if (in) checked[i] = c ? (pos < cap ? 1 : 2) : 0;
+    if (c && pos < cap) ids[pos] = (int32_t)i;
 }
 
 // grid of the remapped kernels: a whole number of XCD rounds (the blocks
@@ -1553,7 +1596,7 @@ hipError_t launch_scalar_eval_fp32(int dim, int blend, const TraceArgs<float>& a
 namespace mlp {
 
 hipError_t launch_select_check(int64_t n, int tile, uint64_t seed, float fraction, int32_t* ids,
-                               unsigned long long* n_ids, unsigned char* checked, hipStream_t s)
+                               unsigned long long* n_ids, int64_t cap, unsigned char* checked, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     if (tile % 64 != 0 || tile > 128 || kListBlock % tile != 0 || n > INT32_MAX) return hipErrorInvalidValue;
@@ -1561,7 +1604,7 @@ hipError_t launch_select_check(int64_t n, int tile, uint64_t seed, float fractio
     const double th = (double)fraction * 4294967296.0;
     const uint32_t thresh = th >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)th;
     select_check_kernel<<<(unsigned)((n + kListBlock - 1) / kListBlock), kListBlock, 0, s>>>(
-        n, tile, (uint32_t)(seed ^ (seed >> 32)), thresh, ids, n_ids, checked);
+        n, tile, (uint32_t)(seed ^ (seed >> 32)), thresh, ids, n_ids, (unsigned long long)cap, checked);
     return hipGetLastError();
 }
 

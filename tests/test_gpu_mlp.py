@@ -45,26 +45,55 @@ def swirl_tracer(level=2, precision=mmoc.MMOC_FP64):
     return wl, tr
 
 
+# Element-wise parity of the matrix-core network with the CPU reference that
+# rounds to bf16 at the same points (W2, W3, a1, a2 forward; dz2, dz3 and
+# the transposed operands backward).  The two differ in
+#   * the fp32 arithmetic of the GPU (fp32 layer 1, fp32 accumulation in the
+#     matrix cores, the GELU from the hardware exp2 and reciprocal, each
+#     good to about 1 ulp): relative differences of order 1e-6 in every
+#     pre-activation;
+#   * bf16 rounding flips: a pre-activation that lies within that 1e-6 of a
+#     bf16 rounding midpoint rounds to the other neighbour on one side.  A
+#     flip moves one operand by one bf16 unit (2^-8 of it), which reaches
+#     an output through one weight and one GELU slope (both below about 1):
+#     about 2^-8 of one product term, a few 1e-3 of the output scale.
+# Hence the bounds: every element within 4e-3 (|ref| + s), s the RMS of the
+# reference outputs (one or two flips), and at least 95% of the elements
+# within 1e-5 (|ref| + s) (no flip: fp32 agreement).  The gradients pass
+# through twice as many rounding points (the backward operands) and sum
+# over the samples of the batch, which averages the flips: every element
+# within 5e-3 (|ref| + s_block), at least 90% within 1e-4.
+def elementwise(got, ref, loose, tight, share, what):
+    s = np.sqrt(np.mean(ref ** 2))
+    rel = np.abs(got - ref) / (np.abs(ref) + s)
+    print("%s: max %.2e, p99 %.2e, p50 %.2e, share within %.0e: %.4f"
+          % (what, rel.max(), np.percentile(rel, 99), np.percentile(rel, 50), tight, (rel <= tight).mean()))
+    assert rel.max() <= loose, what
+    assert (rel <= tight).mean() >= share, what
+
+
 def test_forward_matches_reference():
     wl, tr = swirl_tracer()
-    p = init_params(1)
-    mmoc.mmoc_mlp_set_weights(tr.ctx, p.astype(np.float32))
-    p32 = p.astype(np.float32).astype(np.float64)
-    rng = np.random.default_rng(2)
-    x = rng.uniform(-1, 1, size=(1000, 4))
-    xin = torch.tensor(x, dtype=torch.float32, device="cuda")
-    out = torch.empty((1000, 3), dtype=torch.float32, device="cuda")
-    mmoc.mmoc_mlp_forward(tr.ctx, xin, out)
-    torch.cuda.synchronize()
-    y = out.cpu().numpy().astype(np.float64)
-    x32 = xin.cpu().numpy().astype(np.float64)
-    ref16 = O.mlp_forward(p32, x32, bf16=True)
-    ref64 = O.mlp_forward(p32, x32, bf16=False)
-    s = np.abs(ref64).max()
-    e16 = np.abs(y - ref16).max() / s
-    e64 = np.abs(y - ref64).max() / s
-    print("forward: vs bf16 reference %.2e, vs fp64 %.2e" % (e16, e64))
-    assert e16 <= 5e-3 and e64 <= 3e-2
+    for seed in (1, 5):
+        p = init_params(seed)
+        mmoc.mmoc_mlp_set_weights(tr.ctx, p.astype(np.float32))
+        p32 = p.astype(np.float32).astype(np.float64)
+        rng = np.random.default_rng(seed + 1)
+        n = 4000
+        x = rng.uniform(-1, 1, size=(n, 4))
+        xin = torch.tensor(x, dtype=torch.float32, device="cuda")
+        out = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        mmoc.mmoc_mlp_forward(tr.ctx, xin, out)
+        torch.cuda.synchronize()
+        y = out.cpu().numpy().astype(np.float64)
+        x32 = xin.cpu().numpy().astype(np.float64)
+        ref16 = O.mlp_forward(p32, x32, bf16=True)
+        ref64 = O.mlp_forward(p32, x32, bf16=False)
+        elementwise(y, ref16, 4e-3, 1e-5, 0.95, "forward vs bf16 reference (seed %d)" % seed)
+        # and the bf16 rounding itself: against plain float64 only loosely
+        e64 = np.abs(y - ref64).max() / np.abs(ref64).max()
+        print("forward vs float64: max relative %.2e" % e64)
+        assert e64 <= 3e-2
 
 
 def test_gradients_match_reference():
@@ -80,16 +109,12 @@ def test_gradients_match_reference():
     loss = mmoc.mmoc_mlp_loss_grad(tr.ctx, torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"), g)
     g = g.cpu().numpy().astype(np.float64)
     l16, g16 = O.mlp_loss_grad(p32, x.astype(np.float64), t.astype(np.float64), bf16=True)
-    l64, g64 = O.mlp_loss_grad(p32, x.astype(np.float64), t.astype(np.float64), bf16=False)
     assert abs(loss - l16) <= 1e-3 * l16
-    # per layer block, relative in the 2-norm
+    # element by element within each parameter block (W1, b1, ..., b4)
     blocks = [(0, 256), (256, 320), (320, 4416), (4416, 4480), (4480, 8576), (8576, 8640), (8640, 8832),
               (8832, 8835)]
     for a, b in blocks:
-        r16 = np.linalg.norm(g[a:b] - g16[a:b]) / np.linalg.norm(g16[a:b])
-        r64 = np.linalg.norm(g[a:b] - g64[a:b]) / np.linalg.norm(g64[a:b])
-        print("grad block %d:%d rel vs bf16 ref %.2e, vs fp64 %.2e" % (a, b, r16, r64))
-        assert r16 <= 1e-2 and r64 <= 5e-2
+        elementwise(g[a:b], g16[a:b], 5e-3, 1e-4, 0.9 if b - a > 3 else 0.0, "gradient %d:%d" % (a, b))
 
 
 def record_swirl(tr, wl, steps, dt=None):
