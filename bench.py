@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--surrogate-only", action="store_true", help="only the surrogate legs")
     ap.add_argument("--shell-only", action="store_true",
                     help="only the shell legs of --paths, no oracle (for profiling their kernels)")
+    ap.add_argument("--plume-only", action="store_true",
+                    help="only the trace kernels on the rising plumes, paths from --paths (for profiling them)")
     ap.add_argument("--diffusion-only", action="store_true",
                     help="only the advection-diffusion sub-result (for profiling its kernels)")
     ap.add_argument("--spmv-only", action="store_true",
@@ -182,6 +184,10 @@ def main():
     ELEM_CACHE = 0 if args.no_elem_cache else 1
     if args.surrogate_only:
         print(json.dumps({"surrogate": time_surrogate(S, {})}), flush=True)
+        return
+    if args.plume_only:
+        paths = [p for p in args.paths.split(",") if p in ("fp64", "fp32", "fp32f")]
+        print(json.dumps({"plume3d": time_large(W.plume3d(), 120, paths)}), flush=True)
         return
     paths = args.paths.split(",")
     if "fp64" not in paths:
@@ -624,7 +630,9 @@ def time_large(wl, step, paths, reps=3):
         torch.cuda.synchronize()
         ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
         out["particles"] = tr.N
-        out[names[path]] = {"kernel_ms": ms, "trace_only_particles_per_s": tr.N / (ms * 1e-3)}
+        nb = tr.N * bytes_per_particle(wl.dim, 1 if wl.stationary else 2, 8 if path == "fp64" else 4)
+        out[names[path]] = {"kernel_ms": ms, "trace_only_particles_per_s": tr.N / (ms * 1e-3),
+                            "algorithmic_bytes": nb, "hbm_GBps_algorithmic": nb / (ms * 1e-3) / 1e9}
         tr.close()
         del chat, X
         torch.cuda.empty_cache()

@@ -442,13 +442,11 @@ mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* c, double t_np1, double dt, int 
     mlp_state* S = c->mlp;
     const int64_t N = c->N;
     if ((st = need_aux(c)) != MMOC_OK) return st;
-    // The check sample's RK4 trace depends only on the fields: it runs on the
-    // auxiliary stream while the predictor and the network run on the
-    // context's stream.
-    HIPCHK(c, hipEventRecord(S->ev_fork, c->stream), "fork");
-    HIPCHK(c, hipStreamWaitEvent(S->aux, S->ev_fork, 0), "fork");
-    // 1. the seeded check sample (at least one per tile), then RK4 on it
-    HIPCHK(c, hipMemsetAsync(S->n_ids, 0, sizeof(unsigned long long), S->aux), "clear count");
+    // 1. the seeded check sample (at least one per tile), selected on the
+    //    context's stream before anything else: its blocks of 1,024 threads
+    //    find no room beside a running trace kernel, and beside the
+    //    predictor the selection took up to 3 ms instead of 0.1 ms
+    HIPCHK(c, hipMemsetAsync(S->n_ids, 0, sizeof(unsigned long long), c->stream), "clear count");
     const uint64_t seed = 0x243F6A8885A308D3ull ^ ((uint64_t)step * 0x9E3779B97F4A7C15ull);
     // The list holds up to `cap` particles: twice the expected share plus one
     // per tile, so that the check trace launches a grid of that size
@@ -457,8 +455,13 @@ mmoc_status mmoc_trace_step_surrogate(mmoc_ctx* c, double t_np1, double dt, int 
     // beyond it is not traced and sends its tile to the fallback.
     const int64_t cap = std::min<int64_t>(
         N, 2 * (int64_t)std::ceil((double)check_fraction * (double)N) + (N + kTile - 1) / kTile + 1024);
-    HIPCHK(c, launch_select_check(N, kTile, seed, check_fraction, S->ids, S->n_ids, cap, S->checked, S->aux),
+    HIPCHK(c, launch_select_check(N, kTile, seed, check_fraction, S->ids, S->n_ids, cap, S->checked, c->stream),
            "check sample");
+    // RK4 on the sample depends only on the fields and the list: it runs on
+    // the auxiliary stream while the predictor and the network run on the
+    // context's stream
+    HIPCHK(c, hipEventRecord(S->ev_fork, c->stream), "fork");
+    HIPCHK(c, hipStreamWaitEvent(S->aux, S->ev_fork, 0), "fork");
     TraceExtra on_aux;
     on_aux.stream = S->aux;
     if ((st = mmoc_launch_trace(c, dt, substeps, nullptr, S->Xrk, S->ids, cap, S->n_ids, 0, 1, &on_aux)) != MMOC_OK)

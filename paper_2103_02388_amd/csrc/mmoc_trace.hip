@@ -901,7 +901,11 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
     __shared__ uint4 lcache[CACHE ? Cache::NCH * kTB : 1];
     const MacroGeo* sg = stage_geo(geo, CACHE ? INT_MAX : A.nm, sgeo);
     const int64_t t = logical_block(A.xcd_log2) * kTB + threadIdx.x;
-    const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
+    // a lane traces particle pid: t itself, or the t-th entry of a list
+    // (entries outside [0, N) are skipped)
+    const bool listed = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
+    const int64_t pid = listed && A.order ? (int64_t)A.order[t] : t;
+    const bool active = listed && (uint64_t)pid < (uint64_t)A.xstride;
     unsigned flags = 0;
     uint32_t nlook = 0, nhit = 0;
     Cache cache;
@@ -909,7 +913,6 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
     bool keep = false, chk = false;
     if (A.checked) keep = finish_keep(X, A.xcheck, A.checked, DIM, A.xstride, A.tol_half, t, active, chk, stats);
     if (active) {
-        const int64_t pid = A.order ? (int64_t)A.order[t] : t;
         const uint64_t e = A.owned[pid];
         int M;
         double Y[DIM];
@@ -1240,7 +1243,11 @@ void trace_fp32_kernel(const TraceArgs<float> A)
     __shared__ uint4 lcache[CACHE ? Cache::NCH * kTB : 1];
     const MacroGeo* sg = stage_geo(A.geo, CACHE ? INT_MAX : A.nm, sgeo);
     const int64_t t = logical_block(A.xcd_log2) * kTB + threadIdx.x;
-    const bool active = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
+    // a lane traces particle pid: t itself, or the t-th entry of a list
+    // (entries outside [0, N) are skipped)
+    const bool listed = t < A.n && (!A.n_dev || (unsigned long long)t < *A.n_dev);
+    const int64_t pid = listed && A.order ? (int64_t)A.order[t] : t;
+    const bool active = listed && (uint64_t)pid < (uint64_t)A.xstride;
     unsigned flags = 0;
     uint32_t nlook = 0, nhit = 0;
     Cache cache;
@@ -1248,7 +1255,6 @@ void trace_fp32_kernel(const TraceArgs<float> A)
     bool keep = false, chk = false;
     if (A.checked) keep = finish_keep(A.X, A.xcheck, A.checked, DIM, A.xstride, A.tol_half, t, active, chk, A.stats);
     if (active) {
-        const int64_t pid = A.order ? (int64_t)A.order[t] : t;
         const uint64_t e = A.owned[pid];
         int M;
         double Y[DIM];
@@ -1394,77 +1400,106 @@ __device__ __forceinline__ uint32_t hash32(uint32_t seed, uint32_t i)
     return x;
 }
 
-// Appends the block's lanes with `take` to a list: one atomic per block on
-// the list length (blocks of NT threads, every thread calls).  Returns the
-// lane's index into the list (meaningful where take is set).
-template <int NT>
-__device__ __forceinline__ unsigned long long block_append(unsigned long long* len, bool take)
-{
-    __shared__ unsigned cnt[NT / 64];
-    __shared__ unsigned long long base;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const unsigned long long mask = __ballot(take);
-    if (lane == 0) cnt[wave] = (unsigned)__popcll(mask);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned tot = 0;
-        for (int w = 0; w < NT / 64; ++w) tot += cnt[w];
-        base = tot ? atomicAdd(len, (unsigned long long)tot) : 0ull;
-    }
-    __syncthreads();
-    unsigned before = 0;
-    for (int w = 0; w < wave; ++w) before += cnt[w];
-    const unsigned long long below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
-    return base + before + (unsigned long long)__popcll(below);
-}
-
 constexpr int kListBlock = 1024;
+constexpr int kSelRounds = 16;  // most particles per thread of the selection
 
-// One thread per particle: particle i is checked when its 32-bit hash is
-// below thresh = fraction 2^32 (every particle for fraction 1); a tile (one
-// or two waves, `tile` particles) with no such particle checks its particle
-// of smallest hash (compared in the upper 25 bits; ties: lowest index).
-// Appends the selected particles to the list, up to `cap` entries, and
-// marks them in `checked` (1: in the list, 2: beyond the capacity).
-__global__ __launch_bounds__(kListBlock) void select_check_kernel(int64_t n, int tile, uint32_t seed, uint32_t thresh,
-                                                                  int32_t* ids, unsigned long long* n_ids,
-                                                                  unsigned long long cap, unsigned char* checked)
+// Particle i is checked when its 32-bit hash is below thresh = fraction 2^32
+// (every particle for fraction 1); a tile (one or two waves, `tile`
+// particles) with no such particle checks its particle of smallest hash
+// (compared in the upper 25 bits; ties: lowest index).  Appends the selected
+// particles to the list, up to `cap` entries, and marks them in `checked`
+// (1: in the list, 2: beyond the capacity).  A block takes `rounds` (at
+// most kSelRounds) rounds of kListBlock consecutive particles and reserves
+// its list entries with one atomic: an atomic per 1024 particles on the one
+// list length serialises (16,600 of them at 1.7e7 particles took 0.6 ms),
+// while small launches keep one round per block so that enough blocks run.
+// The list's order is that of the reservations; only the set matters.
+__global__ __launch_bounds__(kListBlock) void select_check_kernel(int64_t n, int tile, int rounds, uint32_t seed,
+                                                                  uint32_t thresh, int32_t* ids,
+                                                                  unsigned long long* n_ids, unsigned long long cap,
+                                                                  unsigned char* checked)
 {
-    __shared__ uint32_t skey[kListBlock / 64];
-    __shared__ int sany[kListBlock / 64];
+    constexpr int NW = kListBlock / 64;
+    __shared__ uint32_t skey[NW];
+    __shared__ int sany[NW];
+    __shared__ unsigned cnt[kSelRounds * NW];  // per (round, wave): count, then its offset in the block's share
+    __shared__ unsigned long long base;
+    static_assert(kSelRounds * NW % 64 == 0, "offsets: whole lanes");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * kListBlock + threadIdx.x;
-    const bool in = i < n;
-    const uint32_t h = hash32(seed, (uint32_t)i);
-    bool c = in && (h < thresh || thresh == 0xFFFFFFFFu);
-    // the tile's smallest hash, made unique by the particle's place in its
-    // tile (tiles are 64 or 128 particles: 7 bits)
-    uint32_t key = in ? ((h & ~127u) | (uint32_t)(i % tile)) : ~0u;
+    const int wpt = tile / 64, w0 = wave - wave % wpt;
+    const int64_t first = (int64_t)blockIdx.x * kListBlock * rounds + threadIdx.x;
+    uint32_t picks = 0;  // bit q: the particle of round q is selected
+    for (int q = 0; q < rounds; ++q) {
+        const int64_t i = first + (int64_t)q * kListBlock;
+        const bool in = i < n;
+        const uint32_t h = hash32(seed, (uint32_t)i);
+        bool c = in && (h < thresh || thresh == 0xFFFFFFFFu);
+        // the tile's smallest hash, made unique by the particle's place in
+        // its tile (tiles are 64 or 128 particles: 7 bits)
+        uint32_t key = in ? ((h & ~127u) | (uint32_t)(i % tile)) : ~0u;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) key = min(key, (uint32_t)__shfl_xor((int)key, off, 64));
-    const bool wany = __ballot(c) != 0;
-    if (lane == 0) {
-        skey[wave] = key;
-        sany[wave] = wany;
+        for (int off = 32; off > 0; off >>= 1) key = min(key, (uint32_t)__shfl_xor((int)key, off, 64));
+        const bool wany = __ballot(c) != 0;
+        if (lane == 0) {
+            skey[wave] = key;
+            sany[wave] = wany;
+        }
+        __syncthreads();
+        bool any = false;
+        uint32_t best = ~0u;
+        for (int w = w0; w < w0 + wpt; ++w) {
+            any |= sany[w] != 0;
+            best = min(best, skey[w]);
+        }
+        if (!any && in && (uint32_t)(i % tile) == (best & 127u)) c = true;
+        picks |= (uint32_t)c << q;
+        const unsigned long long m = __ballot(c);
+        if (lane == 0) cnt[q * NW + wave] = (unsigned)__popcll(m);
+        __syncthreads();  // skey / sany are rewritten by the next round
+    }
+    // unused rounds count zero; every count is written before wave 0 reads
+    // them all
+    for (int e = rounds * NW + (int)threadIdx.x; e < kSelRounds * NW; e += kListBlock) cnt[e] = 0;
+    __syncthreads();
+    // exclusive offsets over (round, wave) in order, by wave 0; one atomic
+    if (wave == 0) {
+        constexpr int PER = kSelRounds * NW / 64;
+        unsigned v[PER], sum = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            v[j] = cnt[lane * PER + j];
+            sum += v[j];
+        }
+        unsigned incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned o = (unsigned)__shfl_up((int)incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        unsigned run = incl - sum;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            cnt[lane * PER + j] = run;
+            run += v[j];
+        }
+        const unsigned tot = (unsigned)__shfl((int)incl, 63, 64);
+        if (lane == 0) base = tot ? atomicAdd(n_ids, (unsigned long long)tot) : 0ull;
     }
     __syncthreads();
-    const int wpt = tile / 64, w0 = wave - wave % wpt;
-    bool any = false;
-    uint32_t best = ~0u;
-    for (int w = w0; w < w0 + wpt; ++w) {
-        any |= sany[w] != 0;
-        best = min(best, skey[w]);
+    const unsigned long long below_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int q = 0; q < rounds; ++q) {
+        const int64_t i = first + (int64_t)q * kListBlock;
+        const bool c = (picks >> q) & 1u;
+        const unsigned long long m = __ballot(c);
+        const unsigned long long pos = base + cnt[q * NW + wave] + (unsigned long long)__popcll(m & below_mask);
+        // a selected particle beyond the list's capacity is marked 2
+        // (selected, not traced): the finish pass sends its tile to the
+        // fallback
+        if (i < n) checked[i] = c ? (pos < cap ? 1 : 2) : 0;
+        if (c && pos < cap) ids[pos] = (int32_t)i;
     }
-    if (!any && in && (uint32_t)(i % tile) == (best & 127u)) c = true;
-    const unsigned long long pos = block_append<kListBlock>(n_ids, c);
-    // a selected particle beyond the list's capacity is marked 2 (selected,
-    // not traced): the finish pass sends its tile to the fallback
-    if (in) checked[i] = c ? (pos < cap ? 1 : 2) : 0;
-    if (c && pos < cap) ids[pos] = (int32_t)i;
 }
 
-// grid of the remapped kernels: a whole number of XCD rounds (the blocks
-// beyond the particle range have no active lane)
 // grid of a remapped launch (a whole number of XCD rounds: blocks beyond the
 // particle range have no active lane) and the run length it uses
 inline unsigned grid_xcd(int64_t n, int lg)
@@ -1603,8 +1638,12 @@ hipError_t launch_select_check(int64_t n, int tile, uint64_t seed, float fractio
     // particle i is checked when hash < fraction 2^32
     const double th = (double)fraction * 4294967296.0;
     const uint32_t thresh = th >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)th;
-    select_check_kernel<<<(unsigned)((n + kListBlock - 1) / kListBlock), kListBlock, 0, s>>>(
-        n, tile, (uint32_t)(seed ^ (seed >> 32)), thresh, ids, n_ids, (unsigned long long)cap, checked);
+    // one round per block up to 256 blocks' worth of particles, then more
+    // rounds per block (at most kSelRounds) instead of more blocks
+    const int rounds = (int)std::min<int64_t>(kSelRounds, std::max<int64_t>(1, n / ((int64_t)kListBlock * 256)));
+    const int64_t per_block = (int64_t)kListBlock * rounds;
+    select_check_kernel<<<(unsigned)((n + per_block - 1) / per_block), kListBlock, 0, s>>>(
+        n, tile, rounds, (uint32_t)(seed ^ (seed >> 32)), thresh, ids, n_ids, (unsigned long long)cap, checked);
     return hipGetLastError();
 }
 

@@ -183,6 +183,66 @@ def test_infinite_tolerance_keeps_the_network():
     assert same_rk.sum() >= st["n_checked"]
 
 
+
+def check_sample(N, step, fraction, tile=128):
+    """The surrogate's check sample, from its definition: particle i is
+    checked when the murmur3 finaliser of (i * 0x9E3779B1) ^ seed is below
+    fraction 2^32 (every particle for fraction 1), seed the 32-bit fold of
+    0x243F6A8885A308D3 ^ step * 0x9E3779B97F4A7C15; an aligned tile of
+    `tile` particles with no such particle checks the one whose hash is
+    smallest in its upper 25 bits (ties: lowest index)."""
+    m64 = (1 << 64) - 1
+    s64 = 0x243F6A8885A308D3 ^ ((step * 0x9E3779B97F4A7C15) & m64)
+    seed = np.uint64((s64 ^ (s64 >> 32)) & 0xFFFFFFFF)
+    i = np.arange(N, dtype=np.uint64)
+    m32 = np.uint64(0xFFFFFFFF)
+    x = ((i * np.uint64(0x9E3779B1)) & m32) ^ seed
+    x ^= x >> np.uint64(16)
+    x = (x * np.uint64(0x85EBCA6B)) & m32
+    x ^= x >> np.uint64(13)
+    x = (x * np.uint64(0xC2B2AE35)) & m32
+    x ^= x >> np.uint64(16)
+    th = float(np.float32(fraction)) * 4294967296.0
+    thresh = 0xFFFFFFFF if th >= 4294967295.0 else int(th)
+    sel = np.ones(N, bool) if thresh == 0xFFFFFFFF else x < np.uint64(thresh)
+    key = (x & np.uint64(0xFFFFFF80)) | (i % np.uint64(tile))
+    for t0 in range(0, N, tile):
+        if not sel[t0:t0 + tile].any():
+            sel[t0 + int(np.argmin(key[t0:t0 + tile]))] = True
+    return sel
+
+
+@pytest.mark.parametrize("level,fraction", [(5, 0.0), (5, 0.01), (5, 0.3), (5, 1.0), (6, 0.01)])
+def test_check_sample_is_the_hash_rule(level, fraction):
+    """Bit-exact check sample on the swirl: level 5 (274,625 particles, one
+    round of 1,024 per selection block, a ragged last block) and level 6
+    (2,146,689 particles, eight rounds per block).  With an infinite
+    tolerance no tile falls back, so a particle carries its RK4 departure
+    point exactly when it was checked and the network's otherwise."""
+    wl, tr = swirl_tracer(level=level)
+    mmoc.mmoc_mlp_set_weights(tr.ctx, init_params(8).astype(np.float32))
+    xt = tr.dof_coords().t().contiguous()
+    tr.set_velocity(0, W.swirl_velocity(xt, 0.3).t().contiguous())
+    tr.set_velocity(1, W.swirl_velocity(xt, 0.3 + wl.dt).t().contiguous())
+    tr.set_scalar(W.two_blobs(xt).contiguous())
+    N = tr.N
+    want = check_sample(N, 17, fraction)
+    tr.reset_stats()
+    _, X = tr.trace_step_surrogate(0.3 + wl.dt, wl.dt, 4, fraction, float("inf"), step=17)
+    st = tr.stats()
+    Xn = tr.mlp_infer(0.3 + wl.dt, wl.dt)
+    _, Xr = tr.trace_step(wl.dt, 4)
+    torch.cuda.synchronize()
+    X, Xn, Xr = X.cpu().numpy(), Xn.cpu().numpy(), Xr.cpu().numpy()
+    rk = np.all(X == Xr, axis=0)
+    net = np.all(X == Xn, axis=0)
+    assert not np.any(rk & net)
+    assert np.all(rk | net)
+    print("fraction %g: %d checked of %d (%d tiles)" % (fraction, want.sum(), N, (N + 127) // 128))
+    assert st["n_fallback"] == 0 and st["n_checked"] == want.sum()
+    assert np.array_equal(rk, want)
+    tr.close()
+
 SWIRL_PERIOD = 2.0 * W.SWIRL_T   # g(t) = cos(pi t / T) repeats after 2T
 
 
