@@ -103,6 +103,35 @@ __device__ __forceinline__ double dotd(const double* a, const double* b)
     else return fma(a[2], b[2], fma(a[0], b[0], a[1] * b[1]));
 }
 
+// 1/a and sqrt(a) for the inverse blending map, from the hardware's
+// reciprocal and reciprocal-square-root estimates: two Newton-Raphson steps
+// for 1/a, and for sqrt(a) the coupled iteration on s ~ sqrt(a), h ~
+// 1/(2 sqrt(a)) (Goldschmidt) with two residual corrections.  Within an
+// ulp or two of the correctly rounded results, without their range
+// scaling: a is a squared radius or a projection, positive and far from
+// the overflow and denormal ranges on a blended shell.
+__device__ __forceinline__ double recip64(double a)
+{
+    double x = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-a, x, 1.0);
+    return fma(x, e, x);
+}
+
+__device__ __forceinline__ double sqrt64(double a)
+{
+    const double g = __builtin_amdgcn_rsq(a);
+    double s = a * g, h = 0.5 * g;
+    const double e = fma(-h, s, 0.5);
+    s = fma(s, e, s);
+    h = fma(h, e, h);
+    double d = fma(-s, s, a);
+    s = fma(d, h, s);
+    d = fma(-s, s, a);
+    return fma(d, h, s);
+}
+
 template <int DIM, int BLEND>
 struct Geo64 {
     double v0[DIM];
@@ -132,8 +161,8 @@ struct Geo64 {
         if constexpr (BLEND) {
             // Phi^-1(z) = z c |z| / (n.z)
             const double nz = dotd<DIM>(pn, y);
-            const double r = sqrt(dotd<DIM>(y, y));
-            const double f = pc * r / nz;
+            const double r = sqrt64(dotd<DIM>(y, y));
+            const double f = pc * r * recip64(nz);
 #pragma unroll
             for (int i = 0; i < DIM; ++i) p[i] = fma(y[i], f, -v0[i]);
         } else {
@@ -1096,8 +1125,8 @@ struct Geo32 {
         float p[DIM];
         if constexpr (BLEND) {
             const double nz = dotd<DIM>(pn, y);
-            const double r = sqrt(dotd<DIM>(y, y));
-            const double f = pc * r / nz;
+            const double r = sqrt64(dotd<DIM>(y, y));
+            const double f = pc * r * recip64(nz);
 #pragma unroll
             for (int i = 0; i < DIM; ++i) p[i] = (float)fma(y[i], f, -v0[i]);
         } else {
