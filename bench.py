@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--surrogate-only", action="store_true", help="only the surrogate legs")
     ap.add_argument("--shell-only", action="store_true",
                     help="only the shell legs of --paths, no oracle (for profiling their kernels)")
+    ap.add_argument("--swirl-only", action="store_true",
+                    help="only the swirl legs of --paths (for profiling their kernels)")
     ap.add_argument("--plume-only", action="store_true",
                     help="only the trace kernels on the rising plumes, paths from --paths (for profiling them)")
     ap.add_argument("--diffusion-only", action="store_true",
@@ -192,6 +194,10 @@ def main():
     paths = args.paths.split(",")
     if "fp64" not in paths:
         paths = ["fp64"] + paths
+    if args.swirl_only:
+        wl = W.swirl3d()
+        print(json.dumps({"swirl3d": {p: time_path(wl, p, S, args.steps, args.warmup) for p in paths}}), flush=True)
+        return
     wl3 = W.shell3d()
     shell = time_shell(wl3, paths, S, args.steps, args.warmup,
                        oracle=not (args.no_cpu_baseline or args.shell_only))

@@ -95,8 +95,10 @@ typedef struct {
                           Lagrange elements).  P1 is not built for blended meshes. */
     int elem_cache;    /* 1 (default): each lane keeps the nodal velocities of its last
                           micro element in LDS and gathers only when the element changes
-                          (stationary runs and float32 records, within one step); 0: gather
-                          at every stage.  Results are bitwise the same either way. */
+                          (3D P2 RK4 traces over one interval: a stationary level, two
+                          float32 levels, or the earlier of two float64 levels, whose
+                          later level is gathered at every stage); 0: gather at every
+                          stage.  Results are bitwise the same either way. */
     int reserved[2];
 } mmoc_options;
 

@@ -689,8 +689,9 @@ __device__ __forceinline__ void nodal_vel(const Levels<T>& Lv, const T* vb, uint
 // first three vertices fix the axis order).  The cached values are the
 // gathered ones, summed in the gather's order, so the results are bitwise
 // those of the uncached kernel.  Used for the raw values of one velocity
-// level (stationary runs) and of two float32 levels, within one interval of
-// the velocity ring (the two levels do not change during the trace).
+// level (stationary runs), of two float32 levels, and of the earlier of two
+// float64 levels in paired u_z records (cached_vel_zp), within one interval
+// of the velocity ring (the two levels do not change during the trace).
 template <typename T, int NV>
 struct ElemCache {
     static constexpr int NCH = (NV * (int)sizeof(T) + 15) / 16;  // 16-byte chunks per lane
@@ -793,6 +794,55 @@ __device__ __forceinline__ void cached_vel(C& cache, const Levels<T>& Lv, uint32
     }
     cache.get(v);
     sum_elem<NLEV, T, R>(v, st.phi, theta, k);
+}
+
+// The same through the cache for two float64 levels in paired u_z records
+// (ZP): a lane keeps only the earlier level's (u_x, u_y) of its element's
+// nodes (20 values, 160 bytes; the two levels do not change during a trace
+// over one interval) and gathers the later level's (u_x, u_y) and the u_z
+// pair at each evaluation: 20 loads instead of 30 on a hit.  Keeping the
+// u_z pair too (40 values) halves the blocks that fit a CU and was slower
+// (4.50 against 3.90 ms on the 1.7e7-particle plumes).  The sums are those
+// of gather_vel, in its order (bitwise the uncached result).
+template <typename C>
+__device__ __forceinline__ void cached_vel_zp(C& cache, const Levels<double>& Lv, const double* vb, uint32_t mbase,
+                                               const Stencil<3, double, 2>& st, double theta, double* k,
+                                               uint32_t& nhit)
+{
+    double v[C::NVP];
+    int idx[10];
+    stencil_idx<3, 2>(st.k, st.r, idx);
+    if (!cache.take(C::key_of(mbase, st.k, st.r))) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            const double2 xe = ldv<double2>(Lv.ea, (mbase + (uint32_t)idx[q]) * 16u);
+            v[2 * q] = xe.x;
+            v[2 * q + 1] = xe.y;
+        }
+        cache.put(v);
+    } else {
+        ++nhit;
+    }
+    cache.get(v);
+    double ua[3] = {0.0, 0.0, 0.0}, ub[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        const uint32_t slot = mbase + (uint32_t)idx[q];
+        const double2 xl = ldv<double2>(Lv.la, slot * 16u);
+        const double2 zz = ldv<double2>(vb, slot * 16u);
+        const double ph = st.phi[q];
+        ua[0] = fma(ph, v[2 * q], ua[0]);
+        ua[1] = fma(ph, v[2 * q + 1], ua[1]);
+        ua[2] = fma(ph, zz.x, ua[2]);
+        ub[0] = fma(ph, xl.x, ub[0]);
+        ub[1] = fma(ph, xl.y, ub[1]);
+        ub[2] = fma(ph, zz.y, ub[2]);
+    }
+    const double z0 = ua[2], z1 = ub[2];
+    ua[2] = Lv.efirst ? z0 : z1;
+    ub[2] = Lv.efirst ? z1 : z0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k[i] = fma(1.0 - theta, ua[i], theta * ub[i]);
 }
 
 template <int DIM, typename T, typename R, int ORD>
@@ -923,9 +973,10 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP
 void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T* __restrict__ c_hat,
                        double* __restrict__ X, unsigned long long* __restrict__ stats)
 {
-    static_assert(!CACHE || (DIM == 3 && ORD == 2 && !GENERIC && !ZP && (NLEV == 1 || sizeof(T) == 4)),
-                  "element cache: 3D P2 RK4, one level or float32 records");
-    using Cache = ElemCache<T, 30 * NLEV>;
+    static_assert(!CACHE || (DIM == 3 && ORD == 2 && !GENERIC &&
+                             (ZP ? NLEV == 2 && sizeof(T) == 8 : (NLEV == 1 || sizeof(T) == 4))),
+                  "element cache: 3D P2 RK4, one level, float32 records or paired float64 levels");
+    using Cache = ElemCache<T, ZP ? 20 : 30 * NLEV>;
     __shared__ MacroGeo sgeo[CACHE ? 1 : kLdsGeo];
     __shared__ uint4 lcache[CACHE ? Cache::NCH * kTB : 1];
     const MacroGeo* sg = stage_geo(geo, CACHE ? INT_MAX : A.nm, sgeo);
@@ -982,7 +1033,8 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
             micro<DIM, double, false, ORD, !CACHE>(s, l0, lmin, A.level_n, st);
             if constexpr (CACHE) {
                 ++nlook;
-                cached_vel<NLEV, T, double>(cache, Lv, mbase, st, theta, k, nhit);
+                if constexpr (ZP) cached_vel_zp(cache, Lv, A.vb, mbase, st, theta, k, nhit);
+                else cached_vel<NLEV, T, double>(cache, Lv, mbase, st, theta, k, nhit);
             } else {
                 gather_vel<DIM, NLEV, T, double, ORD, ZP>(Lv, A.vb, mbase, st, theta, k);
             }
@@ -1554,8 +1606,16 @@ hipError_t launch_trace_f64g(int dim, int blend, const TraceArgs<T>& a0, hipStre
     const dim3 grid(grid_xcd(a.n, a.xcd_log2)), block(kTB);
     const bool st = a.nlev == 1;
     if constexpr (ORD == 2 && !G) {
-        // the element cache: one stationary level, or two float32 levels
-        // within one interval of the ring
+        // the element cache: one stationary level, or two float32 levels or
+        // two float64 levels in paired u_z records, within one interval of
+        // the ring
+        if constexpr (sizeof(T) == 8) {
+            if (a.elem_cache && dim == 3 && !st && a.zs == 2 && a.n_int == 1) {
+                if (blend) trace_fp64_kernel<3, 2, 1, T, false, 2, true, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+                else trace_fp64_kernel<3, 2, 0, T, false, 2, true, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
+                return hipGetLastError();
+            }
+        }
         if (a.elem_cache && dim == 3 && (st || (sizeof(T) == 4 && a.n_int == 1))) {
             if (st) {
                 if (blend) trace_fp64_kernel<3, 1, 1, T, false, 2, false, true><<<grid, block, 0, s>>>(a, a.geo, a.c_hat, a.X, a.stats);
