@@ -351,10 +351,13 @@ mmoc_status mmoc_mlp_infer(mmoc_ctx* ctx, double t_np1, double dt, double* X_dev
 
 /* Surrogate step.  The departure points of all particles come from the
  * network (mmoc_mlp_infer).  A seeded sample of about check_fraction of the
- * particles (hash(seed, step, i) < check_fraction, with at least one per
- * tile of 128 consecutive particles) is re-traced by RK4 with `substeps`
- * sub-steps by the context's own tracer and precision, on the same fields
- * (on a second stream, beside the network).  Every checked particle keeps
+ * particles (a 32-bit hash of (step, i) below check_fraction * 2^32, with
+ * at least one per tile of 128 consecutive particles) is re-traced by RK4
+ * with `substeps` sub-steps by the context's own tracer and precision, on
+ * the same fields (on a second stream, beside the network).  The sample
+ * list holds 2 check_fraction n_unique + n_unique/128 + 1024 entries; a
+ * selected particle beyond it is not traced and its tile falls back.
+ * Every checked particle keeps
  * its RK4 result; every particle of a tile in which some checked residual
  * |Xhat - X_rk4|_inf exceeds tol/2 is re-traced by RK4 (fallback).  Then
  * chat = c_h^n(X) as in mmoc_trace_step.  c_hat_dev: double* for MMOC_FP64
