@@ -918,12 +918,34 @@ __device__ __forceinline__ int own_lat_idx(uint64_t e)
     else return tet_n(I) + tri_n(J) + K;
 }
 
+// A value the whole wave shares (derived from kernel arguments), held in
+// scalar registers so that stage-dependent choices between such values are
+// scalar selects.
+__device__ __forceinline__ double uniform64(double x)
+{
+    int v[2];
+    __builtin_memcpy(v, &x, 8);
+    v[0] = __builtin_amdgcn_readfirstlane(v[0]);
+    v[1] = __builtin_amdgcn_readfirstlane(v[1]);
+    double r;
+    __builtin_memcpy(&r, v, 8);
+    return r;
+}
+
+__device__ __forceinline__ float uniform32(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
 // A particle at rest (zero velocity at its DoF, e.g. on a no-slip wall or a
-// stagnation line) evaluates at its own DoF again and again.  P2
-// interpolation at a node is the nodal value, so such an evaluation needs no
-// location and one nodal load instead of the stencil's gathers.  `home`
-// tracks Y == the DoF position (no departure-point update has changed a
-// bit of it); a stage point y is the DoF when home and y == Y.
+// stagnation line) stays at its DoF.  P2 interpolation at a node is the
+// nodal value, so an evaluation there needs no location and one nodal load.
+// `home` tracks Y == the DoF position (no departure-point update has changed
+// a bit of it): the scalar step then reads the DoF's own value, and the
+// general-tableau loop evaluates a stage point y == Y of such a particle
+// from the nodal values.  (The RK4 chain locates every stage point after the
+// first: a branch around the evaluation costs every wave register copies of
+// the element cache, more than the at-rest lanes save.)
 template <int DIM>
 __device__ __forceinline__ bool same_point(const double* y, const double* x)
 {
@@ -1064,10 +1086,10 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
             for (int i = 0; i < DIM; ++i) Y[i] = src[(int64_t)i * A.xstride + pid];
             home = false;
         }
-        const double h = A.dt / (double)A.substeps;
-        const double hh = 0.5 * h;
-        const double h6 = h / 6.0;
-        const double invS = 1.0 / (double)A.substeps;
+        const double h = uniform64(A.dt / (double)A.substeps);
+        const double hh = uniform64(0.5 * h);
+        const double h6 = uniform64(h / 6.0);
+        const double invS = uniform64(1.0 / (double)A.substeps);
         double s[DIM], l0, lmin;
         Stencil<DIM, double, ORD> st;
         // velocity at stage point y and stage time theta (Sec. 2.3.2: walk
@@ -1129,39 +1151,50 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                     Y[i] = yn;
                 }
             }
-        } else {
-#pragma unroll 1
-            for (int j = 0; j < nsub; ++j) {
-                double ks[DIM], acc[DIM], y[DIM];
+        } else if (nsub > 0) {
+            // RK4 as one chain of 4 S evaluations: evaluation e is stage
+            // e mod 4 of sub-step e / 4, at (j + a_s)/S intervals back
+            // (a_s = 0, 1/2, 1/2, 1; one interval: theta = 1 - (j + a_s)/S).
+            // The first is the particle's own DoF (the nodal value); every
+            // later one is located, so the loop has no divergent branch
+            // around the evaluation (a particle at rest evaluates at its DoF
+            // through the element like any other point).
+            double ks[DIM], acc[DIM], y[DIM];
+            {
+                double theta;
+                const Levels<T> Lv = levels_at<NLEV, T, double>(A, 0.0, theta);
+                nodal_vel<DIM, NLEV, T, double, ZP>(Lv, A.vb, own_slot, theta, ks);
+            }
 #pragma unroll
-                for (int i = 0; i < DIM; ++i) y[i] = Y[i];
+            for (int i = 0; i < DIM; ++i) acc[i] = 0.0;
+            const int neval = 4 * nsub;
 #pragma unroll 1
-                for (int stg = 0; stg < 4; ++stg) {
-                    // stage (j + a_s)/S intervals back, a_s = 0, 1/2, 1/2, 1; one
-                    // interval: theta = 1 - (j + a_s)/S
-                    const double as = stg == 0 ? 0.0 : (stg == 3 ? 1.0 : 0.5);
-                    double theta;
-                    const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)j + as) * invS, theta);
-                    if ((j == 0 && stg == 0) || (home && same_point<DIM>(y, Y))) {
-                        // the stage point is the particle's own DoF
-                        nodal_vel<DIM, NLEV, T, double, ZP>(Lv, A.vb, own_slot, theta, ks);
-                    } else {
-                        velocity(y, Lv, theta, ks);
-                    }
-                    // k1 + 2 k2 + 2 k3 + k4 accumulated in stage order; next stage point
-                    const double wst = (stg == 0 || stg == 3) ? 1.0 : 2.0;
-                    const double cnext = stg == 2 ? h : hh;
+            for (int e = 0; e < neval; ++e) {
+                const int stg = e & 3;
+                // k1 + 2 k2 + 2 k3 + k4 accumulated in stage order; next stage point
+                const double wst = (stg == 0 || stg == 3) ? 1.0 : 2.0;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) acc[i] = fma(wst, ks[i], acc[i]);
+                if (stg == 3) {
 #pragma unroll
                     for (int i = 0; i < DIM; ++i) {
-                        acc[i] = stg == 0 ? ks[i] : fma(wst, ks[i], acc[i]);
-                        y[i] = fma(-cnext, ks[i], Y[i]);
+                        const double yn = fma(-h6, acc[i], Y[i]);
+                        home = home && yn == Y[i];
+                        Y[i] = yn;
+                        y[i] = yn;
+                        acc[i] = 0.0;
                     }
-                }
+                } else {
+                    const double cnext = stg == 2 ? h : hh;
 #pragma unroll
-                for (int i = 0; i < DIM; ++i) {
-                    const double yn = fma(-h6, acc[i], Y[i]);
-                    home = home && yn == Y[i];
-                    Y[i] = yn;
+                    for (int i = 0; i < DIM; ++i) y[i] = fma(-cnext, ks[i], Y[i]);
+                }
+                if (e + 1 < neval) {
+                    const int e1 = e + 1, s1 = e1 & 3;
+                    const double as = s1 == 0 ? 0.0 : (s1 == 3 ? 1.0 : 0.5);
+                    double theta;
+                    const Levels<T> Lv = levels_at<NLEV, T, double>(A, ((double)(e1 >> 2) + as) * invS, theta);
+                    velocity(y, Lv, theta, ks);
                 }
             }
         }
@@ -1405,26 +1438,51 @@ void trace_fp32_kernel(const TraceArgs<float> A)
             home = false;
         }
         const double hd = A.dt / (double)A.substeps;
-        const float h = (float)hd;
-        const float hh = 0.5f * h;
-        const float h6 = h / 6.0f;
-        const double invSd = 1.0 / (double)A.substeps;
+        const float h = uniform32((float)hd);
+        const float hh = uniform32(0.5f * h);
+        const float h6 = uniform32(h / 6.0f);
+        const double invSd = uniform64(1.0 / (double)A.substeps);
         Stencil<DIM, float, ORD> st;
         const int nsub = keep ? 0 : A.substeps * A.n_int;
-#pragma unroll 1
-        for (int j = 0; j < nsub; ++j) {
+        if (nsub > 0) {
+            // one chain of 4 S evaluations, as in the float64 kernel: the
+            // first at the particle's own DoF, every later one located
             float ks[DIM], acc[DIM];
             double y[DIM];
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) y[i] = Y[i];
-#pragma unroll 1
-            for (int stg = 0; stg < 4; ++stg) {
-                const double as = stg == 0 ? 0.0 : (stg == 3 ? 1.0 : 0.5);
+            {
                 float theta;
-                const Levels<float> Lv = levels_at<NLEV, float, float>(A, ((double)j + as) * invSd, theta);
-                if ((j == 0 && stg == 0) || (home && same_point<DIM>(y, Y))) {
-                    nodal_vel<DIM, NLEV, float, float>(Lv, A.vb, own_slot, theta, ks);
+                const Levels<float> Lv = levels_at<NLEV, float, float>(A, 0.0, theta);
+                nodal_vel<DIM, NLEV, float, float>(Lv, A.vb, own_slot, theta, ks);
+            }
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) acc[i] = 0.0f;
+            const int neval = 4 * nsub;
+#pragma unroll 1
+            for (int e = 0; e < neval; ++e) {
+                const int stg = e & 3;
+                const float wst = (stg == 0 || stg == 3) ? 1.0f : 2.0f;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) acc[i] = fmaf(wst, ks[i], acc[i]);
+                if (stg == 3) {
+                    // departure point accumulated in float64
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) {
+                        const double yn = Y[i] - (double)(h6 * acc[i]);
+                        home = home && yn == Y[i];
+                        Y[i] = yn;
+                        y[i] = yn;
+                        acc[i] = 0.0f;
+                    }
                 } else {
+                    const float cnext = stg == 2 ? h : hh;
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) y[i] = Y[i] - (double)(cnext * ks[i]);
+                }
+                if (e + 1 < neval) {
+                    const int e1 = e + 1, s1 = e1 & 3;
+                    const double as = s1 == 0 ? 0.0 : (s1 == 3 ? 1.0 : 0.5);
+                    float theta;
+                    const Levels<float> Lv = levels_at<NLEV, float, float>(A, ((double)(e1 >> 2) + as) * invSd, theta);
                     locate32<DIM, BLEND, ORD, !CACHE>(A, M, mbase, y, st, flags, sg);
                     if constexpr (CACHE) {
                         ++nlook;
@@ -1433,20 +1491,6 @@ void trace_fp32_kernel(const TraceArgs<float> A)
                         gather_vel<DIM, NLEV, float, float>(Lv, A.vb, mbase, st, theta, ks);
                     }
                 }
-                const float wst = (stg == 0 || stg == 3) ? 1.0f : 2.0f;
-                const float cnext = stg == 2 ? h : hh;
-#pragma unroll
-                for (int i = 0; i < DIM; ++i) {
-                    acc[i] = stg == 0 ? ks[i] : fmaf(wst, ks[i], acc[i]);
-                    y[i] = Y[i] - (double)(cnext * ks[i]);
-                }
-            }
-            // departure point accumulated in float64
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) {
-                const double yn = Y[i] - (double)(h6 * acc[i]);
-                home = home && yn == Y[i];
-                Y[i] = yn;
             }
         }
         float v;

@@ -96,9 +96,10 @@ def test_small_meshes_and_large_steps_fp32():
 def test_tie_band_widths():
     """No band, the default band and a band that sends every location to
     float64 all stay within tolerance; the wide band matches float64 closely.
-    Particles at rest (zero velocity at their DoF: the swirl vanishes on the
-    cube's faces) evaluate at their own node and never locate, so the wide
-    band counts every other particle."""
+    Every particle locates its stage points after the first (particles at
+    rest too: the swirl vanishes on the cube's faces, and their P2 sums at
+    their own node stay exactly zero, so they do not move), so the wide band
+    counts every particle."""
     wl = W.swirl3d()
     res = {}
     for name, em, eu in (("none", 0.0, 0.0), ("default", None, None), ("micro", 4e-6, 2.0 ** -18),
@@ -118,7 +119,7 @@ def test_tie_band_widths():
     assert res["none"][1] == 0
     assert res["micro"][1] > res["default"][1]
     assert 0 < at_rest < p.tr.N // 4
-    assert res["all"][1] == p.tr.N - at_rest
+    assert res["all"][1] == p.tr.N
 
 
 def test_shell_fp32():
