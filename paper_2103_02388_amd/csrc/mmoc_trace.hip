@@ -1000,10 +1000,25 @@ __device__ __forceinline__ void count_cache(unsigned long long* stats, uint32_t 
 // Surrogate finish: the tile's checked particles decide whether it keeps
 // the surrogate's departure points (every thread of the block must call).
 // Counts the checked particles and the largest residual into the stats.
+// Whether any thread of the block has p (every thread must call).  word:
+// a 4-byte LDS word the block does not use otherwise until this returns
+// (the trace kernels lend the first word of their cache array, which their
+// traces write only later; a library reduction would take LDS of its own).
+__device__ __forceinline__ bool block_any(bool p, unsigned* word)
+{
+    if (threadIdx.x == 0) *word = 0u;
+    __syncthreads();
+    if (__ballot(p) != 0 && (threadIdx.x & 63) == 0) atomicOr(word, 1u);
+    __syncthreads();
+    const bool any = *word != 0u;
+    __syncthreads();
+    return any;
+}
+
 __device__ __forceinline__ bool finish_keep(const double* __restrict__ X, const double* __restrict__ xc,
                                             const unsigned char* __restrict__ checked, int dim, int64_t xstride,
                                             double tol_half, int64_t pid, bool active, bool& chk,
-                                            unsigned long long* stats)
+                                            unsigned long long* stats, unsigned* lds_word)
 {
     const unsigned char cv = active ? checked[pid] : 0;
     chk = cv == 1;
@@ -1015,7 +1030,7 @@ __device__ __forceinline__ bool finish_keep(const double* __restrict__ X, const 
         }
         if (r != r) r = INFINITY;
     }
-    const bool keep = !__syncthreads_or(cv != 0 && !(r <= tol_half));
+    const bool keep = !block_any(cv != 0 && !(r <= tol_half), lds_word);
     // one atomic per wave for the count and the largest residual (the bits of
     // a non-negative double order like the double)
     unsigned long long bits;
@@ -1053,9 +1068,12 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
                              (ZP ? NLEV == 2 && sizeof(T) == 8 : (NLEV == 1 || sizeof(T) == 4))),
                   "element cache: 3D P2 RK4, one level, float32 records or paired float64 levels");
     using Cache = std::conditional_t<NLEV == 1 && sizeof(T) == 8, ElemCacheSplit, ElemCache<T, ZP ? 20 : 30 * NLEV>>;
-    __shared__ MacroGeo sgeo[CACHE ? 1 : kLdsGeo];
+    // the cached kernels keep no geometry in LDS (their whole LDS budget is
+    // the cache: the unused array is not allocated)
+    __shared__ MacroGeo sgeo[kLdsGeo];
     __shared__ uint4 lcache[CACHE ? Cache::NCH * kTB : 1];
-    const MacroGeo* sg = stage_geo(geo, CACHE ? INT_MAX : A.nm, sgeo);
+    const MacroGeo* sg = nullptr;
+    if constexpr (!CACHE) sg = stage_geo(geo, A.nm, sgeo);
     const int64_t t = logical_block(A.xcd_log2) * kTB + threadIdx.x;
     // a lane traces particle pid: t itself, or the t-th entry of a list
     // (entries outside [0, N) are skipped)
@@ -1067,7 +1085,9 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
     Cache cache;
     if constexpr (CACHE) cache.init(lcache);
     bool keep = false, chk = false;
-    if (A.checked) keep = finish_keep(X, A.xcheck, A.checked, DIM, A.xstride, A.tol_half, t, active, chk, stats);
+    if (A.checked)
+        keep = finish_keep(X, A.xcheck, A.checked, DIM, A.xstride, A.tol_half, t, active, chk, stats,
+                           reinterpret_cast<unsigned*>(lcache));
     if (active) {
         const uint64_t e = A.owned[pid];
         int M;
@@ -1407,9 +1427,10 @@ void trace_fp32_kernel(const TraceArgs<float> A)
 {
     static_assert(!CACHE || (DIM == 3 && ORD == 2), "element cache: 3D P2");
     using Cache = ElemCache<float, 30 * NLEV>;
-    __shared__ MacroGeo sgeo[CACHE ? 1 : kLdsGeo];
+    __shared__ MacroGeo sgeo[kLdsGeo];
     __shared__ uint4 lcache[CACHE ? Cache::NCH * kTB : 1];
-    const MacroGeo* sg = stage_geo(A.geo, CACHE ? INT_MAX : A.nm, sgeo);
+    const MacroGeo* sg = nullptr;
+    if constexpr (!CACHE) sg = stage_geo(A.geo, A.nm, sgeo);
     const int64_t t = logical_block(A.xcd_log2) * kTB + threadIdx.x;
     // a lane traces particle pid: t itself, or the t-th entry of a list
     // (entries outside [0, N) are skipped)
@@ -1421,7 +1442,9 @@ void trace_fp32_kernel(const TraceArgs<float> A)
     Cache cache;
     if constexpr (CACHE) cache.init(lcache);
     bool keep = false, chk = false;
-    if (A.checked) keep = finish_keep(A.X, A.xcheck, A.checked, DIM, A.xstride, A.tol_half, t, active, chk, A.stats);
+    if (A.checked)
+        keep = finish_keep(A.X, A.xcheck, A.checked, DIM, A.xstride, A.tol_half, t, active, chk, A.stats,
+                           reinterpret_cast<unsigned*>(lcache));
     if (active) {
         const uint64_t e = A.owned[pid];
         int M;
