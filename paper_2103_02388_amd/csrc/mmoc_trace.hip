@@ -50,7 +50,9 @@
 #endif
 // occupancy floors: the float64 kernels need at least 3 waves per SIMD
 // without spilling (the RK4 kernel fits 4 at 128 VGPRs), the float32-mixed
-// kernel 4
+// kernel 4; the cached float64-arithmetic kernels ask for 4 (their 20 KB of
+// LDS per block allow 4; where the LDS allows fewer the compiler keeps more
+// registers)
 #ifndef MMOC_WPE_FP64
 #define MMOC_WPE_FP64 3
 #endif
@@ -1060,7 +1062,7 @@ __device__ __forceinline__ bool finish_keep(const double* __restrict__ X, const 
 // float32 levels); the block's LDS then holds the cache instead of the
 // geometry copy.
 template <int DIM, int NLEV, int BLEND, typename T, bool GENERIC, int ORD, bool ZP = false, bool CACHE = false>
-__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(MMOC_WPE_FP64)))
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(CACHE ? 4 : MMOC_WPE_FP64)))
 void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T* __restrict__ c_hat,
                        double* __restrict__ X, unsigned long long* __restrict__ stats)
 {
