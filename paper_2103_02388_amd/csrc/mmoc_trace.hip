@@ -741,9 +741,8 @@ struct ElemCache {
 
 // The cache of one float64 level: (u_x, u_y) of the element's nodes in LDS
 // (160 B per lane, one chunk per node), u_z in ten registers.  With all 30
-// values in LDS (240 B) five blocks of 128 lanes fit a CU; split, seven fit
-// and the registers allow six (150 VGPRs): 26.9 against 29.7 ms on the
-// 1.7e8-particle shell.
+// values in LDS (240 B) five blocks of 128 lanes fit a CU; split, eight fit
+// (20 KB each) and the kernel's registers allow them.
 struct ElemCacheSplit {
     static constexpr int NCH = 10;
     static constexpr int NVP = 30;
