@@ -544,7 +544,8 @@ struct Levels {
     const T* eb;
     const T* la;  // later level
     const T* lb;
-    uint32_t zb;  // bytes per slot in the vb records
+    uint32_t zsh;  // log2 of the bytes per slot in the vb records (a shift: the
+                   // slot's byte offset without an integer multiply)
     bool efirst;  // paired u_z records (two-level float64 ring): the earlier level is ring slot 0
 };
 
@@ -570,19 +571,19 @@ __device__ __forceinline__ Levels<T> levels_at(const TraceArgs<T>& A, double pos
         L.eb = A.vb + (int64_t)early * A.lsb;
         L.efirst = early == 0;
     }
-    L.zb = (uint32_t)((A.zs > 1 ? A.zs : 1) * sizeof(T));
+    L.zsh = (A.zs > 1 ? 1u : 0u) + (sizeof(T) == 8 ? 3u : 2u);  // zs is 1 or 2
     return L;
 }
 
-// velocity vector of one level (records va, vb; zb bytes per vb slot) at slot q
+// velocity vector of one level (records va, vb; 2^zsh bytes per vb slot) at slot q
 template <int DIM, typename T>
-__device__ __forceinline__ void load_vec(const T* va, const T* vb, uint32_t zb, uint32_t q, T* u)
+__device__ __forceinline__ void load_vec(const T* va, const T* vb, uint32_t zsh, uint32_t q, T* u)
 {
     if constexpr (sizeof(T) == 8) {
         const double2 xy = ldv<double2>(va, q * 16u);
         u[0] = xy.x;
         u[1] = xy.y;
-        if constexpr (DIM == 3) u[2] = ldv<double>(vb, q * zb);
+        if constexpr (DIM == 3) u[2] = ldv<double>(vb, q << zsh);
     } else if constexpr (DIM == 3) {
         const F3 v = ldv<F3>(va, q * 12u);
         u[0] = v.x;
@@ -616,8 +617,8 @@ __device__ __forceinline__ void load_levels(const Levels<T>& Lv, const T* vb, ui
         b[1] = xl.y;
         b[2] = zz.y;
     } else {
-        load_vec<DIM, T>(Lv.ea, Lv.eb, Lv.zb, q, a);
-        if constexpr (NLEV == 2) load_vec<DIM, T>(Lv.la, Lv.lb, Lv.zb, q, b);
+        load_vec<DIM, T>(Lv.ea, Lv.eb, Lv.zsh, q, a);
+        if constexpr (NLEV == 2) load_vec<DIM, T>(Lv.la, Lv.lb, Lv.zsh, q, b);
     }
 }
 
@@ -800,8 +801,8 @@ __device__ __forceinline__ void fetch_elem(const Levels<T>& Lv, uint32_t mbase, 
 #pragma unroll
     for (int q = 0; q < 10; ++q) {
         const uint32_t slot = mbase + (uint32_t)idx[q];
-        load_vec<3, T>(Lv.ea, Lv.eb, Lv.zb, slot, v + q * 3 * NLEV);
-        if constexpr (NLEV == 2) load_vec<3, T>(Lv.la, Lv.lb, Lv.zb, slot, v + q * 6 + 3);
+        load_vec<3, T>(Lv.ea, Lv.eb, Lv.zsh, slot, v + q * 3 * NLEV);
+        if constexpr (NLEV == 2) load_vec<3, T>(Lv.la, Lv.lb, Lv.zsh, slot, v + q * 6 + 3);
     }
 #pragma unroll
     for (int i = 30 * NLEV; i < NVP; ++i) v[i] = T(0);
