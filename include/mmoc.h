@@ -99,7 +99,13 @@ typedef struct {
                           float32 levels, or the earlier of two float64 levels, whose
                           later level is gathered at every stage); 0: gather at every
                           stage.  Results are bitwise the same either way. */
-    int reserved[2];
+    int keep_chat;     /* 1: every trace call that writes chat for all particles also
+                          writes it into a second block-layout scalar array of the
+                          library, which mmoc_use_last_chat then makes the scalar of
+                          the next step (a time-stepping run then ingests no scalar;
+                          allocates one more scalar array and the interface slot list
+                          at mmoc_upload_mesh).  0 (default): off. */
+    int reserved;
 } mmoc_options;
 
 typedef struct {
@@ -174,6 +180,14 @@ mmoc_status mmoc_swap_velocity_levels(mmoc_ctx* ctx);
 /* Sets the scalar c_h^n from a unique-layout [n_unique] float64 device array
  * (copied into the block layout). */
 mmoc_status mmoc_set_scalar(mmoc_ctx* ctx, const double* c_dev);
+
+/* The scalar of the next step is the chat of the last trace call that wrote
+ * chat for all particles (options.keep_chat = 1): the same block-layout
+ * values mmoc_set_scalar(chat) would ingest, without the ingestion.  The
+ * scalar array of the step before becomes the one the next trace writes.
+ * MMOC_E_STATE if keep_chat is off or no such trace call ran since the last
+ * mmoc_use_last_chat. */
+mmoc_status mmoc_use_last_chat(mmoc_ctx* ctx);
 
 /* mmoc_set_velocity(ctx, level, u_dev) and mmoc_set_scalar(ctx, c_dev) in
  * one pass over the block layout: the field ingestion of a time step

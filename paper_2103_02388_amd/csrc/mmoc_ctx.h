@@ -41,6 +41,12 @@ struct mmoc_ctx {
     int lev_cap = 2;
     int rot = 0;
     void* cs_d = nullptr;                // scalar
+    // options.keep_chat: the next step's scalar written by the trace (own
+    // slots) and completed from the interface slot list (owner slot, slot)
+    void* cs_next = nullptr;
+    int32_t* dup_d = nullptr;
+    int64_t ndup = 0;
+    bool chat_ready = false;
     std::vector<char> vel_set = std::vector<char>(2, 0);  // per logical level
     bool scalar_set = false;
     bool stationary = false;

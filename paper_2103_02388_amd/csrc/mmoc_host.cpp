@@ -217,7 +217,8 @@ mmoc_status mmoc_create(mmoc_ctx** out, int dim, int level, mmoc_precision prec,
     if (level < 0 || level > 10 || (dim == 3 && level > 9)) return MMOC_E_ARG;  // lattice index fits int32
     if (prec != MMOC_FP64 && prec != MMOC_FP32_MIXED && prec != MMOC_FP32_FIELDS) return MMOC_E_ARG;
     if (opt && (!(opt->eps_in >= 0) || opt->max_hops < 0 || !(opt->eps32_macro >= 0) || !(opt->eps32_micro >= 0) ||
-                opt->order < 0 || opt->order > 2 || opt->elem_cache < 0 || opt->elem_cache > 1))
+                opt->order < 0 || opt->order > 2 || opt->elem_cache < 0 || opt->elem_cache > 1 ||
+                opt->keep_chat < 0 || opt->keep_chat > 1))
         return MMOC_E_ARG;
     mmoc_ctx* c = new (std::nothrow) mmoc_ctx();
     if (!c) return MMOC_E_NOMEM;
@@ -440,6 +441,8 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
     std::vector<int32_t> slot_uid((size_t)nm * npm);
     std::vector<uint64_t> owned;
     owned.reserve((size_t)nm * npm);
+    std::vector<int32_t> own_slot;  // the slot where each DoF is owned (keep_chat)
+    const bool keep = c->opt.keep_chat != 0;
     int64_t N = 0;
     for (int M = 0; M < nm; ++M) {
         int64_t idx = 0;
@@ -460,6 +463,7 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
                     if (Mo == M) {
                         u = (int32_t)N++;
                         owned.push_back(mmoc::pack_owned((uint32_t)M, (uint32_t)I, (uint32_t)J, (uint32_t)K));
+                        if (keep) own_slot.push_back((int32_t)((int64_t)M * npm + idx));
                     } else {
                         // weights in the owner's local vertex order
                         int wo[4] = {0, 0, 0, 0};
@@ -493,10 +497,28 @@ mmoc_status mmoc_upload_mesh(mmoc_ctx* c, int nv, const double* vert, int nm, co
     const size_t elem = f32 ? sizeof(float) : sizeof(double);
     if ((st = alloc_velocity_levels(c, c->lev_cap)) != MMOC_OK) return st;
     if ((st = alloc_clear(c, &c->cs_d, (size_t)c->nslots * elem, "scalar array")) != MMOC_OK) return st;
+    std::vector<int32_t> dup;
+    if (keep) {
+        // the interface slots, each with the slot of its DoF's owner
+        for (int64_t t = 0; t < c->nslots; ++t) {
+            const int32_t o = own_slot[(size_t)slot_uid[(size_t)t]];
+            if (o != (int32_t)t) {
+                dup.push_back(o);
+                dup.push_back((int32_t)t);
+            }
+        }
+        c->ndup = (int64_t)dup.size() / 2;
+        if ((st = alloc_clear(c, &c->cs_next, (size_t)c->nslots * elem, "next scalar array")) != MMOC_OK) return st;
+        if (c->ndup > 0 && (st = dev_alloc(c, &c->dup_d, dup.size(), "interface slot list")) != MMOC_OK) return st;
+    }
+    c->chat_ready = false;
     HIPCHK(c, hipMemcpyAsync(c->geo_d, geo.data(), sizeof(MacroGeo) * nm, hipMemcpyHostToDevice, c->stream), "upload geometry");
     HIPCHK(c, hipMemcpyAsync(c->owned_d, owned.data(), sizeof(uint64_t) * N, hipMemcpyHostToDevice, c->stream), "upload particles");
     HIPCHK(c, hipMemcpyAsync(c->slot_uid_d, slot_uid.data(), sizeof(int32_t) * c->nslots, hipMemcpyHostToDevice, c->stream),
            "upload slot map");
+    if (!dup.empty())
+        HIPCHK(c, hipMemcpyAsync(c->dup_d, dup.data(), sizeof(int32_t) * dup.size(), hipMemcpyHostToDevice, c->stream),
+               "upload interface slot list");
     HIPCHK(c, hipStreamSynchronize(c->stream), "mesh upload");
     c->geo_h = std::move(geo);
     c->mesh_ok = true;
@@ -630,6 +652,18 @@ mmoc_status mmoc_set_scalar(mmoc_ctx* c, const double* cs)
     return MMOC_OK;
 }
 
+mmoc_status mmoc_use_last_chat(mmoc_ctx* c)
+{
+    if (!c) return MMOC_E_ARG;
+    if (!c->mesh_ok) return fail(c, MMOC_E_STATE, "no mesh uploaded");
+    if (!c->opt.keep_chat) return fail(c, MMOC_E_STATE, "options.keep_chat is off");
+    if (!c->chat_ready) return fail(c, MMOC_E_STATE, "no trace call has written chat since the last use");
+    std::swap(c->cs_d, c->cs_next);
+    c->chat_ready = false;
+    c->scalar_set = true;
+    return MMOC_OK;
+}
+
 }  // extern "C"
 
 // Shared by the plain and the surrogate step: launches the RK4 tracer on n
@@ -672,6 +706,10 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.xcheck = ex ? ex->xcheck : nullptr;
         a.tol_half = ex ? ex->tol_half : 0.0;
     };
+    // keep_chat: a call that writes chat for every particle also writes the
+    // next step's block-layout scalar (the trace kernel at each DoF's own
+    // slot, then the interface slots from their owners)
+    void* c_next = (c->opt.keep_chat && c_hat && !order && !n_dev && n == c->N) ? c->cs_next : nullptr;
     if (c->prec != MMOC_FP64) {
         mmoc::TraceArgs<float> a{};
         fill(a);
@@ -679,6 +717,7 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.vb = (const float*)c->vb_all;
         a.cs = (const float*)c->cs_d;
         a.c_hat = (float*)c_hat;
+        a.c_next = (float*)c_next;
         if (c->prec == MMOC_FP32_MIXED)
             HIPCHK(c, mmoc::launch_trace_fp32(c->dim, c->blend, a, stream), "trace (fp32 mixed)");
         else
@@ -690,7 +729,12 @@ mmoc_status mmoc_launch_trace(mmoc_ctx* c, double dt, int substeps, void* c_hat,
         a.vb = (const double*)c->vb_all;
         a.cs = (const double*)c->cs_d;
         a.c_hat = (double*)c_hat;
+        a.c_next = (double*)c_next;
         HIPCHK(c, mmoc::launch_trace_fp64(c->dim, c->blend, a, stream), "trace (fp64)");
+    }
+    if (c_next) {
+        HIPCHK(c, mmoc::launch_dup_fill(c_next, c->prec != MMOC_FP64, c->dup_d, c->ndup, stream), "next scalar");
+        c->chat_ready = true;
     }
     return MMOC_OK;
 }
@@ -822,6 +866,8 @@ void free_all(mmoc_ctx* c)
     (void)hipFree(c->vb_all);
     c->va_all = c->vb_all = nullptr;
     (void)hipFree(c->cs_d);
+    (void)hipFree(c->cs_next);
+    (void)hipFree(c->dup_d);
     (void)hipFree(c->stats_d);
     (void)hipFree(c->red_d);
     c->red_d = nullptr;
@@ -830,6 +876,10 @@ void free_all(mmoc_ctx* c)
     c->owned_d = nullptr;
     c->slot_uid_d = nullptr;
     c->cs_d = nullptr;
+    c->cs_next = nullptr;
+    c->dup_d = nullptr;
+    c->ndup = 0;
+    c->chat_ready = false;
     c->stats_d = nullptr;
 }
 }  // namespace

@@ -128,6 +128,7 @@ struct TraceArgs {
     const double* xcheck;
     double tol_half;
     T* c_hat;                // [n_unique] or null
+    T* c_next;               // block-layout scalar of the next step: chat at each DoF's own slot, or null
     double* X;               // [dim][n_unique] or null
     unsigned long long* stats;
     RKTab rk;                // float64-arithmetic kernels only
@@ -136,6 +137,8 @@ struct TraceArgs {
 // Launchers (kernels in mmoc_kernels.hip).  Each validates nothing: the host
 // side checks every argument before calling them.
 hipError_t launch_trace_fp64(int dim, int blend, const TraceArgs<double>& a, hipStream_t s);
+// v[dup[2i + 1]] = v[dup[2i]] for i < ndup (interface slots from their owner's slot)
+hipError_t launch_dup_fill(void* v, int fp32, const int32_t* dup, int64_t ndup, hipStream_t s);
 hipError_t launch_trace_fp32(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);
 // float32 records, float64 arithmetic (MMOC_FP32_FIELDS)
 hipError_t launch_trace_fp32_fields(int dim, int blend, const TraceArgs<float>& a, hipStream_t s);

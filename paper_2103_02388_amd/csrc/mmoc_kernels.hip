@@ -64,6 +64,16 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int ncomp, const int32_
     (void)nu;
 }
 
+// interface slots of the next step's scalar from their owners' slots
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dup_fill_kernel(T* __restrict__ v, const int2* __restrict__ dup, int64_t ndup)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= ndup) return;
+    const int2 p = dup[t];
+    v[p.y] = v[p.x];
+}
+
 inline unsigned grid_plain(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -77,6 +87,15 @@ hipError_t launch_dof_coords(int dim, int blend, const MacroGeo* geo, const uint
     else if (dim == 2) dof_coords_kernel<2, 1><<<grid, block, 0, s>>>(geo, owned, n, lat_m, out);
     else if (!blend) dof_coords_kernel<3, 0><<<grid, block, 0, s>>>(geo, owned, n, lat_m, out);
     else dof_coords_kernel<3, 1><<<grid, block, 0, s>>>(geo, owned, n, lat_m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dup_fill(void* v, int fp32, const int32_t* dup, int64_t ndup, hipStream_t s)
+{
+    if (ndup <= 0) return hipSuccess;
+    const int2* p = reinterpret_cast<const int2*>(dup);
+    if (fp32) dup_fill_kernel<float><<<grid_plain(ndup), kBlock, 0, s>>>(static_cast<float*>(v), p, ndup);
+    else dup_fill_kernel<double><<<grid_plain(ndup), kBlock, 0, s>>>(static_cast<double*>(v), p, ndup);
     return hipGetLastError();
 }
 

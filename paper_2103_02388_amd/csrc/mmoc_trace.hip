@@ -1244,6 +1244,7 @@ void trace_fp64_kernel(const TraceArgs<T> A, const MacroGeo* __restrict__ geo, T
         for (int i = 0; i < DIM; ++i) bad |= Y[i] != Y[i];
         if (bad) flags |= LF_NAN;
         if (c_hat) c_hat[pid] = (T)v;
+        if (A.c_next) A.c_next[own_slot] = (T)v;
         if (X) {
 #pragma unroll
             for (int i = 0; i < DIM; ++i) X[(int64_t)i * A.xstride + pid] = Y[i];
@@ -1530,6 +1531,7 @@ void trace_fp32_kernel(const TraceArgs<float> A)
         for (int i = 0; i < DIM; ++i) bad |= Y[i] != Y[i];
         if (bad) flags |= LF_NAN;
         if (A.c_hat) A.c_hat[pid] = v;
+        if (A.c_next) A.c_next[own_slot] = v;
         if (A.X) {
 #pragma unroll
             for (int i = 0; i < DIM; ++i) A.X[(int64_t)i * A.xstride + pid] = Y[i];

@@ -38,7 +38,7 @@ EXPORTED = [
     "mmoc_destroy", "mmoc_mlp_forward", "mmoc_mlp_loss_grad", "mmoc_mass_inner", "mmoc_mass_inner_noalloc", "mmoc_field_range",
     "mmoc_lookback_run", "mmoc_set_rk_tableau", "mmoc_cfl_time_step", "mmoc_set_level_count", "mmoc_trace_span",
     "mmoc_fe_assemble", "mmoc_fe_export", "mmoc_fe_apply", "mmoc_boundary_mask", "mmoc_diffusion_step",
-    "mmoc_set_fields",
+    "mmoc_set_fields", "mmoc_use_last_chat",
 ]
 
 
@@ -50,7 +50,8 @@ class MMOCError(RuntimeError):
 
 class mmoc_options(C.Structure):
     _fields_ = [("eps_in", C.c_double), ("eps32_macro", C.c_float), ("eps32_micro", C.c_float),
-                ("max_hops", C.c_int), ("order", C.c_int), ("elem_cache", C.c_int), ("reserved", C.c_int * 2)]
+                ("max_hops", C.c_int), ("order", C.c_int), ("elem_cache", C.c_int), ("keep_chat", C.c_int),
+                ("reserved", C.c_int)]
 
 
 class mmoc_stats(C.Structure):
@@ -100,6 +101,7 @@ def lib():
         "mmoc_set_stationary": (st, [P, I]),
         "mmoc_swap_velocity_levels": (st, [P]),
         "mmoc_set_scalar": (st, [P, P]),
+        "mmoc_use_last_chat": (st, [P]),
         "mmoc_set_fields": (st, [P, I, P, P]),
         "mmoc_trace_step": (st, [P, D, I, P, P]),
         "mmoc_get_stats": (st, [P, C.POINTER(mmoc_stats)]),
@@ -209,6 +211,10 @@ def mmoc_swap_velocity_levels(ctx):
 
 def mmoc_set_scalar(ctx, c: torch.Tensor):
     _check(ctx, lib().mmoc_set_scalar(ctx, _ptr(c)))
+
+
+def mmoc_use_last_chat(ctx):
+    _check(ctx, lib().mmoc_use_last_chat(ctx))
 
 
 def mmoc_set_fields(ctx, level, u: torch.Tensor, c: torch.Tensor):
@@ -437,6 +443,10 @@ class Tracer:
 
     def set_scalar(self, c):
         mmoc_set_scalar(self.ctx, c)
+
+    def use_last_chat(self):
+        """the next step's scalar is the last step's chat (options.keep_chat)"""
+        mmoc_use_last_chat(self.ctx)
 
     def set_fields(self, level, u, c):
         """velocity level and scalar in one ingestion pass"""

@@ -32,6 +32,7 @@ def test_default_options_and_param_count():
     from paper_2103_02388_amd import mmoc
     o = mmoc.mmoc_default_options()
     assert o.eps_in == 1e-12 and o.max_hops == 64
+    assert o.elem_cache == 1 and o.keep_chat == 0
     assert mmoc.mmoc_mlp_nparams() == 4 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * 3 + 3
 
 
