@@ -329,6 +329,14 @@ __device__ __forceinline__ int tet_n(int x) { return (x * (x + 1) * (x + 2)) / 6
 // are the vertices on the lattice of resolution n, P2 node (a, b) sits at
 // V_a + V_b on the lattice of resolution 2n (vertex nodes a = b first,
 // then the edges a < b).
+//
+// P2: along axis x node (a, b), a <= b, has the doubled coordinate
+// 2 k_x + [r_x < b] + [r_x < a].  The lattice index is a sum of one term
+// per axis, and from 2 k_x that term grows by P_x at the first unit and
+// by a further Q_x at the second.  So idx(a, b) = base + Pc(b) + Qc(a),
+// with Pc(t) and Qc(t) the sums of P_x and Q_x over the axes of rank below
+// t: a few selects by rank per element instead of per node (base is
+// carried in Qc below).
 template <int DIM, int ORD>
 __device__ __forceinline__ void stencil_idx(const int* k, const int* r, int* idx)
 {
@@ -345,42 +353,49 @@ __device__ __forceinline__ void stencil_idx(const int* k, const int* r, int* idx
             idx[a] = id;
         }
     } else {
-        // 2k + delta with delta_i = [r_i < a] + [r_i < b] in {0,1,2}
-        const int I0 = 2 * k[0], J0 = 2 * k[1], K0 = 2 * k[2];
-        int TI[3], TJ[3];
+        const int I0 = 2 * k[0], J0 = 2 * k[1];
+        int base, P[DIM], Q[DIM];
         if constexpr (DIM == 3) {
-            TI[0] = tet_n(I0);
-            TI[1] = TI[0] + tri_n(I0 + 1);
-            TI[2] = TI[1] + tri_n(I0 + 2);
-            TJ[0] = tri_n(J0);
-            TJ[1] = TJ[0] + J0 + 1;
-            TJ[2] = TJ[1] + J0 + 2;
+            base = tet_n(I0) + tri_n(J0) + 2 * k[2];
+            P[0] = tri_n(I0 + 1);
+            Q[0] = tri_n(I0 + 2);
+            P[1] = J0 + 1;
+            Q[1] = J0 + 2;
+            P[2] = 1;
+            Q[2] = 1;
         } else {
-            TI[0] = tri_n(I0);
-            TI[1] = TI[0] + I0 + 1;
-            TI[2] = TI[1] + I0 + 2;
-            TJ[0] = J0;
-            TJ[1] = J0 + 1;
-            TJ[2] = J0 + 2;
+            base = tri_n(I0) + J0;
+            P[0] = I0 + 1;
+            Q[0] = I0 + 2;
+            P[1] = 1;
+            Q[1] = 1;
         }
-        auto node = [&](int a, int b) {
-            const int dI = (r[0] < a) + (r[0] < b);
-            const int dJ = (r[1] < a) + (r[1] < b);
-            if constexpr (DIM == 3) {
-                const int dK = (r[2] < a) + (r[2] < b);
-                return (dI == 0 ? TI[0] : (dI == 1 ? TI[1] : TI[2])) + (dJ == 0 ? TJ[0] : (dJ == 1 ? TJ[1] : TJ[2])) +
-                       K0 + dK;
-            } else {
-                return (dI == 0 ? TI[0] : (dI == 1 ? TI[1] : TI[2])) + (dJ == 0 ? TJ[0] : (dJ == 1 ? TJ[1] : TJ[2]));
-            }
+        // the value of the axis of rank j
+        auto by_rank = [&](const int* v, int j) {
+            if constexpr (DIM == 3) return r[0] == j ? v[0] : (r[1] == j ? v[1] : v[2]);
+            else return r[0] == j ? v[0] : v[1];
         };
+        int Pc[DIM + 1], Qc[DIM + 1];
+        Pc[0] = 0;
+        Qc[0] = base;
+#pragma unroll
+        for (int t = 1; t < DIM; ++t) {
+            Pc[t] = Pc[t - 1] + by_rank(P, t - 1);
+            Qc[t] = Qc[t - 1] + by_rank(Q, t - 1);
+        }
+        Pc[DIM] = P[0] + P[1];
+        Qc[DIM] = base + Q[0] + Q[1];
+        if constexpr (DIM == 3) {
+            Pc[DIM] += P[2];
+            Qc[DIM] += Q[2];
+        }
         int c = 0;
 #pragma unroll
-        for (int a = 0; a <= DIM; ++a) idx[c++] = node(a, a);
+        for (int a = 0; a <= DIM; ++a) idx[c++] = Qc[a] + Pc[a];
 #pragma unroll
         for (int a = 0; a <= DIM; ++a)
 #pragma unroll
-            for (int b = a + 1; b <= DIM; ++b) idx[c++] = node(a, b);
+            for (int b = a + 1; b <= DIM; ++b) idx[c++] = Qc[a] + Pc[b];
     }
 }
 
