@@ -495,7 +495,7 @@ def time_path(wl, path, S, steps, warmup):
 
 def surrogate_run(wl, vel, train, run, box_hi, U, period, prec_name="fp64", S=4, tol=1e-4, pred=1, scale=1e-4,
                   scalar=None):
-    """The learned flow-map surrogate in a time loop (the run of config 4):
+    """The learned flow-map surrogate in a time loop:
     steps `train` (step n covers [t_{n-1}, t_n]) traced by RK4 with S
     sub-steps and recorded, the network trained on 2e6 pairs drawn from
     them (30 epochs), then steps `run` with the surrogate step (1% check
@@ -577,28 +577,29 @@ def surrogate_run(wl, vel, train, run, box_hi, U, period, prec_name="fp64", S=4,
 
 
 def time_surrogate(S, swirl):
-    """Config 4 on the swirl (trained on steps 1-10, steps 11-110) and its
-    full-period variant (trained on steps 1-40, one period of the velocity;
-    steps 41-140); config 5's surrogate leg on the rising plumes (trained on
-    steps 1-10, steps 11-200)."""
+    """The swirl run (level 5, 274,625 particles; trained on steps 1-10,
+    steps 11-110) and its full-period variant (trained on steps 1-40, one
+    period of the velocity; steps 41-140); the rising plumes (level 7,
+    16,974,593 particles; trained on steps 1-10, steps 11-200), with float64
+    and with float32 records."""
     from paper_2103_02388_amd import workloads as W
     wl = W.swirl3d(steps=140)
     per = 2.0 * W.SWIRL_T
-    out = {"swirl3d_config4": surrogate_run(wl, W.swirl_velocity, range(1, 11), range(11, 111), per, 2.0, per, S=S),
+    out = {"swirl3d_train_1_10_run_11_110": surrogate_run(wl, W.swirl_velocity, range(1, 11), range(11, 111), per, 2.0, per, S=S),
            "swirl3d_full_period": surrogate_run(wl, W.swirl_velocity, range(1, 41), range(41, 141), per, 2.0, per,
                                                 S=S)}
     if "fp64" in swirl:
-        for k in ("swirl3d_config4", "swirl3d_full_period"):
+        for k in ("swirl3d_train_1_10_run_11_110", "swirl3d_full_period"):
             out[k]["speedup_vs_fp64_swirl_trace"] = swirl["fp64"]["kernel_ms"] / out[k]["surrogate_ms"]
     pl = W.plume3d()
-    out["plume3d_config5"] = surrogate_run(pl, pl.velocity, range(1, 11), range(11, 201), pl.extra["T"],
+    out["plume3d_train_1_10_run_11_200"] = surrogate_run(pl, pl.velocity, range(1, 11), range(11, 201), pl.extra["T"],
                                            pl.extra["umax"], 0.0, S=S)
     # the same with float32 records (predictor, check and fallback through
     # the element cache), against the float32-fields and float64 RK4 steps
     f = surrogate_run(pl, pl.velocity, range(1, 11), range(11, 201), pl.extra["T"], pl.extra["umax"], 0.0, S=S,
                       prec_name="fp32f")
-    f["speedup_vs_fp64_rk4"] = out["plume3d_config5"]["rk4_ms"] / f["surrogate_ms"]
-    out["plume3d_config5_fp32_fields"] = f
+    f["speedup_vs_fp64_rk4"] = out["plume3d_train_1_10_run_11_200"]["rk4_ms"] / f["surrogate_ms"]
+    out["plume3d_train_1_10_run_11_200_fp32_fields"] = f
     return out
 
 

@@ -248,7 +248,7 @@ SWIRL_PERIOD = 2.0 * W.SWIRL_T   # g(t) = cos(pi t / T) repeats after 2T
 
 def swirl_surrogate_run(train, run, prec=mmoc.MMOC_FP64, pred=1, scale=1e-4, tol=1e-4, n_check=4000,
                         epochs=30, samples=2_000_000, timing=False):
-    """The swirl run with the surrogate (config 4): steps `train` (1-based
+    """The swirl run with the surrogate: steps `train` (1-based
     step n covers [t_{n-1}, t_n]) traced by RK4 (4 sub-steps) and recorded,
     the network trained on `samples` pairs drawn from them, then steps `run`
     with the surrogate (1% check sample, tolerance tol).  The network learns
@@ -349,8 +349,8 @@ def report(tag, out, tol):
     return kept
 
 
-def test_surrogate_config4_trained_on_steps_1_to_10():
-    """Config 4 as specified: steps 1-10 traced and recorded, then steps
+def test_surrogate_swirl_trained_on_steps_1_to_10_run_11_to_110():
+    """The swirl (level 5, 274,625 particles): steps 1-10 traced and recorded, then steps
     11-110 with the 1% check at tol 1e-4.  The network corrects the
     one-sub-step RK4 trace (whose own error against 4 sub-steps is up to
     1.4e-4 on this flow); its time input is the phase of the periodic
@@ -370,7 +370,7 @@ def test_surrogate_config4_trained_on_steps_1_to_10():
         oracle's P2 evaluation there)."""
     tol = 1e-4
     out = swirl_surrogate_run(range(1, 11), range(11, 111), tol=tol)
-    report("config 4 (train 1-10)", out, tol)
+    report("swirl, train 1-10, run 11-110", out, tol)
     for r in out["rows"]:
         assert r["above"] < 0.01, r
         assert r["err"] <= 2 * tol, r
