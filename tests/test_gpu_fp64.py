@@ -171,6 +171,72 @@ def test_shell_blended_fp64():
     assert p.tr.stats()["n_nan"] == 0
 
 
+def test_shell3d_full_size_sampled_fp64():
+    """The headline workload in the launch configuration the benchmark times:
+    the spherical shell at full size (3840 macros at level 5, 168,428,034
+    particles), stationary seeded flow, float64 with the element cache on
+    (the default options), RK4 with 4 sub-steps.  The analytic fields are
+    evaluated once at the oracle's DoF positions and the same arrays go to
+    both sides; the library's own DoF positions are compared on the sample.
+    The oracle traces a seeded sample of 3000 particles.
+
+    X to 1e-12 relative.  chat: the scalar is a step at r = 0.8 plus 1%
+    nodal noise, so its P2 interpolant has slopes up to about
+    L = 6 / (h/2) (a jump of 1 across half a radial micro edge h, P2
+    shape-function gradients at most 3 / height, a factor 2 for the element
+    shape); a last-bit difference in X moves chat by up to L times it, so
+    chat is held to 1e-12 * L + 1e-14 on the sample, and to 1e-12 (relative)
+    away from the step (departure radius more than 0.02 from 0.8).  A smooth
+    scalar is traced as well, held to 1e-12 relative everywhere."""
+    from oracle import oracle as O
+    wl = W.shell3d()
+    tr = mmoc.Tracer.from_workload(wl, precision=mmoc.MMOC_FP64, options=mmoc.mmoc_default_options())
+    om = O.Mesh.from_workload(wl)
+    N = om.N
+    assert tr.N == N == 168_428_034
+    ids = np.sort(np.random.default_rng(15).choice(N, 3000, replace=False))
+    xc = om.dof_coords()
+    idt = torch.from_numpy(ids).cuda()
+    xg = tr.dof_coords()
+    assert np.abs(xg[:, idt].cpu().numpy() - xc[:, ids]).max() < 1e-14
+    del xg
+    xt = torch.from_numpy(np.ascontiguousarray(xc.T)).cuda()
+    u = wl.velocity(xt).t().contiguous()
+    c = wl.scalar0(xt).contiguous()
+    smooth = (xt[:, 0] ** 2 + xt[:, 1] * xt[:, 2]).contiguous()
+    del xt
+    tr.set_stationary(True)
+    tr.set_velocity(0, u)
+    tr.set_scalar(c)
+    tr.reset_stats()
+    ch, X = tr.trace_step(wl.dt, 4)
+    torch.cuda.synchronize()
+    st = tr.stats()
+    assert st["n_nan"] == 0 and st["n_particles"] == N
+    assert st["n_cache_lookups"] > 0 and st["n_cache_hits"] > 0.5 * st["n_cache_lookups"]
+    Xs, chs = X[:, idt].cpu().numpy(), ch[idt].cpu().numpy()
+    tr.set_scalar(smooth)
+    ch2, _ = tr.trace_step(wl.dt, 4, want_X=False)
+    ch2s = ch2[idt].cpu().numpy()
+    uc, cc, sc = u.cpu().numpy(), c.cpu().numpy(), smooth.cpu().numpy()
+    del u, c, smooth, X, ch, ch2
+    tr.close()
+    chr_, Xr, _ = om.trace(uc, None, cc, wl.dt, 4, ids=ids, threads=8)
+    ch2r, _, _ = om.trace(uc, None, sc, wl.dt, 4, ids=ids, threads=8)
+    ex = rel_x(Xs, Xr)
+    assert ex <= TOL, ex
+    L = 6.0 / (wl.extra["h_min"] / 2)
+    ec_all = np.abs(chs - chr_).max()
+    assert ec_all <= TOL * L + 1e-14, ec_all
+    far = np.abs(np.linalg.norm(Xr, axis=0) - 0.8) > 0.02
+    ec = rel_c(chs[far], chr_[far])
+    assert ec <= TOL, ec
+    es = rel_c(ch2s, ch2r)
+    assert es <= TOL, es
+    print("fp64 shell %d particles: X %.2e, chat %.2e (all %.2e, bound %.1e), smooth chat %.2e, cache hits %.3f"
+          % (N, ex, ec, ec_all, TOL * L + 1e-14, es, st["n_cache_hits"] / st["n_cache_lookups"]))
+
+
 def test_nan_velocity_is_counted_and_contained():
     wl = W.swirl3d()
     p = Pair(wl, level=2)
