@@ -99,3 +99,59 @@ def test_plume3d_full_size_sampled_fp32_fields():
     chr_, Xr, _ = p.oracle_step(wl.dt, 4, ids=ids, threads=8)
     assert rel_x(X[:, ids], Xr) <= TOL_X
     assert np.abs(ch[ids] - chr_).max() <= TOL_X * 10.0 + 1e-6
+
+
+def test_shell3d_full_size_sampled_fp32_fields():
+    """The spherical shell at full size (168,428,034 particles) in the
+    benchmark's launch configuration for this path (element cache on),
+    against the float64 oracle on a seeded sample of 3000 particles; the same
+    float64 field arrays go to both sides (the library rounds them to its
+    float32 records).  X within 1e-6 relative.  chat away from the step at
+    r = 0.8 (departure radius more than 0.02 from it) within
+    1e-6 * max(1, L) + 1e-6, with L = 0.02 * 6 / (h/2) bounding the slope the
+    1% nodal noise gives the P2 interpolant (as for the float32-mixed
+    tracer); a smooth scalar (|grad| <= 3) within 1e-6 * 3 + 1e-6."""
+    from oracle import oracle as O
+    wl = W.shell3d()
+    tr = mmoc.Tracer.from_workload(wl, precision=PREC, options=mmoc.mmoc_default_options())
+    om = O.Mesh.from_workload(wl)
+    N = om.N
+    assert tr.N == N == 168_428_034
+    ids = np.sort(np.random.default_rng(16).choice(N, 3000, replace=False))
+    xc = om.dof_coords()
+    idt = torch.from_numpy(ids).cuda()
+    xg = tr.dof_coords()
+    assert np.abs(xg[:, idt].cpu().numpy() - xc[:, ids]).max() < 1e-14
+    del xg
+    xt = torch.from_numpy(np.ascontiguousarray(xc.T)).cuda()
+    u = wl.velocity(xt).t().contiguous()
+    c = wl.scalar0(xt).contiguous()
+    smooth = (xt[:, 0] ** 2 + xt[:, 1] * xt[:, 2]).contiguous()
+    del xt
+    tr.set_stationary(True)
+    tr.set_velocity(0, u)
+    tr.set_scalar(c)
+    tr.reset_stats()
+    ch, X = tr.trace_step(wl.dt, 4)
+    torch.cuda.synchronize()
+    st = tr.stats()
+    assert st["n_nan"] == 0 and st["n_particles"] == N
+    Xs, chs = X[:, idt].cpu().numpy(), ch[idt].double().cpu().numpy()
+    tr.set_scalar(smooth)
+    ch2, _ = tr.trace_step(wl.dt, 4, want_X=False)
+    ch2s = ch2[idt].double().cpu().numpy()
+    uc, cc, sc = u.cpu().numpy(), c.cpu().numpy(), smooth.cpu().numpy()
+    del u, c, smooth, X, ch, ch2
+    tr.close()
+    chr_, Xr, _ = om.trace(uc, None, cc, wl.dt, 4, ids=ids, threads=8)
+    ch2r, _, _ = om.trace(uc, None, sc, wl.dt, 4, ids=ids, threads=8)
+    ex = rel_x(Xs, Xr)
+    assert ex <= TOL_X, ex
+    L = 0.02 * 6 / (wl.extra["h_min"] / 2)
+    far = np.abs(np.linalg.norm(Xr, axis=0) - 0.8) > 0.02
+    ec = np.abs(chs[far] - chr_[far]).max()
+    assert ec <= TOL_X * max(1.0, L) + 1e-6, (ec, L)
+    es = np.abs(ch2s - ch2r).max()
+    assert es <= TOL_X * 3 + 1e-6, es
+    print("fp32-fields shell %d particles: X %.2e, chat %.2e (bound %.1e), smooth chat %.2e"
+          % (N, ex, ec, TOL_X * max(1.0, L) + 1e-6, es))
