@@ -150,9 +150,12 @@ def test_plume3d_full_size_sampled_fp32():
     assert np.abs(ch[ids] - chr_).max() <= chat_tol(10.0)
 
 
-def test_shell3d_full_size_sampled_fp32():
+@pytest.mark.parametrize("micro_band", [0.0, 2.0 ** -18])
+def test_shell3d_full_size_sampled_fp32(micro_band):
     """The spherical shell at full size: 3840 macros at level 5, 168,428,034
-    particles, stationary seeded flow, float32-mixed.  The analytic fields are
+    particles, stationary seeded flow, float32-mixed, with the micro tie band
+    off (the default) and at 2^-18 (the float64 micro decision within
+    2^-18 * n of a tie), the two configurations the benchmark times.  The analytic fields are
     evaluated once, at the oracle's DoF positions (torch on the GPU, the
     seeded input generator), and the same arrays go to both sides; the
     library's own DoF positions are compared on the sample.  The oracle traces
@@ -167,7 +170,9 @@ def test_shell3d_full_size_sampled_fp32():
     shape), so |dchat| <= 1e-5 * that + 1e-6.  A smooth scalar (|grad| <= 3
     on the shell) is traced as well, with the tight bound 3e-5 + 2e-6."""
     wl = W.shell3d()
-    tr = mmoc.Tracer.from_workload(wl, precision=mmoc.MMOC_FP32_MIXED)
+    opt = mmoc.mmoc_default_options()
+    opt.eps32_micro = micro_band
+    tr = mmoc.Tracer.from_workload(wl, precision=mmoc.MMOC_FP32_MIXED, options=opt)
     om = O.Mesh.from_workload(wl)
     N = om.N
     assert tr.N == N == 168_428_034
@@ -213,7 +218,7 @@ def test_shell3d_full_size_sampled_fp32():
     assert ec <= TOL_X * L + 1e-6
     es = np.abs(ch2s - ch2r).max()
     assert es <= 3e-5 + 2e-6
-    print("fp32 shell %d particles: trace %.2f ms (%.3g particles/s), X %.2e, chat %.2e (bound %.1e), "
-          "smooth chat %.2e, tieband %.4f, multi-hop %d, outside %d"
-          % (N, ms, N / (ms * 1e-3), ex, ec, TOL_X * L + 1e-6, es, st["n_tieband"] / st["n_particles"],
-             st["n_multi_hop"], st["n_outside"]))
+    print("fp32 shell (micro band %g) %d particles: trace %.2f ms (%.3g particles/s), X %.2e, "
+          "chat %.2e (bound %.1e), smooth chat %.2e, tieband %.4f, multi-hop %d, outside %d"
+          % (micro_band, N, ms, N / (ms * 1e-3), ex, ec, TOL_X * L + 1e-6, es,
+             st["n_tieband"] / st["n_particles"], st["n_multi_hop"], st["n_outside"]))
