@@ -36,9 +36,12 @@ from paper_2103_02388_amd import workloads as W
 
 
 class Columns:
-    """The shell's macro columns from the vertex and macro lists."""
+    """The macro columns of a blended shell (3D: cones of three unit
+    directions) or annulus (2D: sectors of two) from the vertex and macro
+    lists."""
 
     def __init__(self, v, m):
+        d = v.shape[1]
         unit = v / np.linalg.norm(v, axis=1, keepdims=True)
         key = {}
         cols = []
@@ -46,16 +49,20 @@ class Columns:
             ds = []
             for a in mac:
                 q = unit[a]
-                if not any(np.abs(q - d).sum() < 1e-9 for d in ds):
+                if not any(np.abs(q - e).sum() < 1e-9 for e in ds):
                     ds.append(q)
-            assert len(ds) == 3
-            k = tuple(sorted(tuple(np.round(d * 1e9).astype(np.int64)) for d in ds))
+            assert len(ds) == d
+            k = tuple(sorted(tuple(np.round(e * 1e9).astype(np.int64)) for e in ds))
             if k not in key:
                 key[k] = len(cols)
                 cols.append(np.array(ds))
-        D = np.stack(cols)                       # [C, 3 directions, 3]
+        D = np.stack(cols)                       # [C, d directions, d]
         self.Dinv = np.linalg.inv(np.transpose(D, (0, 2, 1)))   # y = D^T alpha
-        n = np.cross(D[:, 1] - D[:, 0], D[:, 2] - D[:, 0])
+        if d == 3:
+            n = np.cross(D[:, 1] - D[:, 0], D[:, 2] - D[:, 0])
+        else:                                    # normal of the chord between the two directions
+            e = D[:, 1] - D[:, 0]
+            n = np.stack([-e[:, 1], e[:, 0]], axis=1)
         n /= np.linalg.norm(n, axis=1, keepdims=True)
         c = np.einsum("ci,ci->c", n, D[:, 0])
         s = np.where(c < 0, -1.0, 1.0)
@@ -127,6 +134,34 @@ def test_shell_trace_with_velocity_affine_in_the_computational_coordinates(level
     assert np.all(np.abs(np.linalg.norm(X, axis=0) - r[ids]) < 1e-6)   # tangential
     assert ex <= 1e-12
     assert ec <= 1e-12
+
+
+def test_annulus_trace_with_velocity_affine_in_the_computational_coordinates():
+    """The same pin in 2D on the blended annulus of the diffusion benchmark
+    (6 sectors, levels 4 and 5): u = J xi with J the quarter turn, tangent to
+    the circles.  The DoFs on the inner and outer circles are left out."""
+    v, m = W.annulus()
+    cols = Columns(v, m)
+    assert len(cols.c) == 6 and np.all(cols.c > 0)
+    J = np.array([[0.0, -1.0], [1.0, 0.0]])
+    for level in (4, 5):
+        wl = W.annulus2d(level=level)
+        om = O.Mesh.from_workload(wl)
+        x = om.dof_coords().T.copy()
+        xi = cols.phi_inv(x)
+        r = np.linalg.norm(x, axis=1)
+        interior = np.nonzero((r > 0.5 + 1e-9) & (r < 1.5 - 1e-9))[0]
+        u_nodes = xi @ J.T
+        ids = np.sort(np.random.default_rng(level).choice(interior, 6000, replace=False))
+        dt = 0.3                                 # several macros' worth of walk per step
+        ch, X, st = om.trace(u_nodes.T, None, xi[:, 0], dt, 4, ids=ids, threads=8)
+        Xr = rk4_reference(cols, J, np.zeros(2), x[ids], dt, 4)
+        ex = np.abs(X.T - Xr).max()
+        ec = np.abs(ch - cols.phi_inv(X.T)[:, 0]).max()
+        print("annulus level %d: %d particles, walks %d, |X - X_ref| %.2e, |chat - xi0(X)| %.2e"
+              % (level, len(ids), st[1], ex, ec))
+        assert st[1] > 0 and st[0] == 0
+        assert ex <= 1e-12 and ec <= 1e-12
 
 
 def test_reference_column_map_is_continuous_and_exact_on_the_directions():
