@@ -164,6 +164,53 @@ def test_annulus_trace_with_velocity_affine_in_the_computational_coordinates():
         assert ex <= 1e-12 and ec <= 1e-12
 
 
+def test_shell_trace_between_two_velocity_levels():
+    """Two velocity levels u^n = A1 xi, u^{n+1} = A2 xi (both antisymmetric),
+    linear in time: at sub-step j and RK4 node a the tracer takes the later
+    level with weight theta = 1 - (j + a) / S (the trace runs back from
+    t_{n+1}), so the mesh-free reference integrates
+    u(y, theta) = ((1 - theta) A1 + theta A2) Phi^-1(y) with those weights."""
+    wl = W.shell3d(level=1)
+    v, m = W.shell(4, 4)
+    cols = Columns(v, m)
+    om = O.Mesh.from_workload(wl)
+    x = om.dof_coords().T.copy()
+    xi = cols.phi_inv(x)
+    r = np.linalg.norm(x, axis=1)
+    A1 = A0 / np.abs(xi @ A0.T).max()
+    K = np.array([[0.0, 0.4, -1.0], [-0.4, 0.0, 0.6], [1.0, -0.6, 0.0]])
+    A2 = K / np.abs(xi @ K.T).max()
+    interior = np.nonzero((r > 0.55 + 1e-9) & (r < 1.0 - 1e-9))[0]
+    ids = np.sort(np.random.default_rng(5).choice(interior, 8000, replace=False))
+    S, dt = 4, wl.dt
+    ch, X, st = om.trace((xi @ A1.T).T, (xi @ A2.T).T, xi[:, 0], dt, S, ids=ids, threads=8)
+    h = dt / S
+
+    def u(y, theta):
+        return cols.phi_inv(y) @ ((1.0 - theta) * A1 + theta * A2).T
+    Y = x[ids].copy()
+    for j in range(S):
+        k1 = u(Y, 1.0 - j / S)
+        k2 = u(Y - 0.5 * h * k1, 1.0 - (j + 0.5) / S)
+        k3 = u(Y - 0.5 * h * k2, 1.0 - (j + 0.5) / S)
+        k4 = u(Y - h * k3, 1.0 - (j + 1.0) / S)
+        Y = Y - h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    ex = np.abs(X.T - Y).max()
+    ec = np.abs(ch - cols.phi_inv(X.T)[:, 0]).max()
+    # the other direction of the time weights is far off
+    Yw = x[ids].copy()
+    for j in range(S):
+        k1 = u(Yw, j / S)
+        k2 = u(Yw - 0.5 * h * k1, (j + 0.5) / S)
+        k3 = u(Yw - 0.5 * h * k2, (j + 0.5) / S)
+        k4 = u(Yw - h * k3, (j + 1.0) / S)
+        Yw = Yw - h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    print("two levels: walks %d, |X - X_ref| %.2e, |chat - xi0(X)| %.2e, reversed weights %.2e"
+          % (st[1], ex, ec, np.abs(X.T - Yw).max()))
+    assert st[0] == 0 and ex <= 1e-12 and ec <= 1e-12
+    assert np.abs(X.T - Yw).max() > 1e-3
+
+
 def test_reference_column_map_is_continuous_and_exact_on_the_directions():
     """The reference Phi^-1 itself: the identity on the column directions'
     rays through the macro vertices, continuous across column faces (points
