@@ -1345,9 +1345,11 @@ __device__ __forceinline__ float ref32_at(const MacroGeo* __restrict__ geo, int 
 
 // The float64 re-evaluation of one location: with `walk`, the macro walk in
 // float64 (a macro tie or a macro change), then the micro element in float64
-// (shape functions handed back in float32).  Out of line: it runs for a
-// small fraction of the evaluations and must not cost the hot loop registers.
-template <int DIM, int BLEND, int ORD>
+// (shape functions handed back in float32; node indices only with IDX, the
+// cached kernels take them from the element's base cell and axis ranks).
+// Out of line: it runs for a small fraction of the evaluations and must not
+// cost the hot loop registers.
+template <int DIM, int BLEND, int ORD, bool IDX = true>
 __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int nm, int max_hops, double eps, int M,
                                           int level_n, int walk, double y0, double y1, double y2,
                                           Stencil<DIM, float, ORD>* out)
@@ -1362,10 +1364,10 @@ __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int 
     const double l0 = G.ref(y, s);
     const double lmin = lam_min<DIM, double>(l0, s);
     Stencil<DIM, double, ORD> st;
-    micro<DIM, double, false, ORD>(s, l0, lmin, level_n, st);
+    micro<DIM, double, false, ORD, IDX>(s, l0, lmin, level_n, st);
 #pragma unroll
     for (int q = 0; q < Stencil<DIM, double, ORD>::NN; ++q) {
-        out->idx[q] = st.idx[q];
+        if constexpr (IDX) out->idx[q] = st.idx[q];
         out->phi[q] = (float)st.phi[q];
     }
 #pragma unroll
@@ -1430,8 +1432,8 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint
     if (redo) {
         if (!macro_redo || lmin > -A.eps32_macro) flags |= LF_TIEBAND;
         Stencil<DIM, float, ORD> s64;
-        const unsigned r = locate64<DIM, BLEND, ORD>(A.geo, A.nm, A.max_hops, A.eps_in, M, A.level_n, macro_redo, y[0],
-                                                y[1], DIM == 3 ? y[DIM - 1] : 0.0, &s64);
+        const unsigned r = locate64<DIM, BLEND, ORD, IDX>(A.geo, A.nm, A.max_hops, A.eps_in, M, A.level_n, macro_redo, y[0],
+                                                     y[1], DIM == 3 ? y[DIM - 1] : 0.0, &s64);
         flags |= r >> 27;
         M = (int)(r & ((1u << 27) - 1));
         mbase = (uint32_t)M * (uint32_t)A.npm;
