@@ -1343,8 +1343,9 @@ __device__ __forceinline__ float ref32_at(const MacroGeo* __restrict__ geo, int 
     return G.ref(y, s);
 }
 
-// The float64 re-evaluation of one location: with `walk`, the macro walk in
-// float64 (a macro tie or a macro change), then the micro element in float64
+// The float64 re-evaluation of a location whose macro float32 could not
+// decide: with `walk`, the macro walk in float64, then the micro element in
+// float64
 // (shape functions handed back in float32; node indices only with IDX, the
 // cached kernels take them from the element's base cell and axis ranks).
 // Out of line: it runs for a small fraction of the evaluations and must not
@@ -1381,9 +1382,11 @@ __device__ __noinline__ unsigned locate64(const MacroGeo* __restrict__ geo, int 
 // Location of a stage point in float32.  A macro decision that float32
 // cannot take with certainty -- the smallest barycentric within eps32_macro
 // of zero on a face that has a neighbour, or a macro change -- is re-taken
-// in float64, and so is a micro decision within eps32_micro * n of a tie.
-// Near a boundary face there is no second macro to choose: the point stays,
-// and its element is selected from the clamped barycentrics as in float64.
+// in float64, and so is a micro decision within eps32_micro * n of a tie
+// (in line: the macro is certain then, so only its float64 barycentrics and
+// the micro element from them are needed).  Near a boundary face there is no
+// second macro to choose: the point stays, and its element is selected from
+// the clamped barycentrics as in float64.
 template <int DIM, int BLEND, int ORD, bool IDX = true>
 __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint32_t& mbase, const double* y,
                                          Stencil<DIM, float, ORD>& st, unsigned& flags, const MacroGeo* sg = nullptr)
@@ -1424,7 +1427,26 @@ __device__ __forceinline__ void locate32(const TraceArgs<float>& A, int& M, uint
     if (!macro_redo) {
         if (A.eps32_micro > 0.0f) {
             const float gap = micro<DIM, float, true, ORD, IDX>(s, l0, lmin, A.level_n, st);
-            redo = gap < A.eps32_micro * (float)A.level_n;
+            if (gap < A.eps32_micro * (float)A.level_n) {
+                // a micro tie in a certain macro: the float64 barycentrics
+                // of this macro and the micro element from them, in line
+                flags |= LF_TIEBAND;
+                double s64[DIM];
+                const double l064 = ref_at<DIM, BLEND>(A.geo, M, y, s64, sg);
+                const double lmin64 = lam_min<DIM, double>(l064, s64);
+                Stencil<DIM, double, ORD> st64;
+                micro<DIM, double, false, ORD, IDX>(s64, l064, lmin64, A.level_n, st64);
+#pragma unroll
+                for (int q = 0; q < Stencil<DIM, double, ORD>::NN; ++q) {
+                    st.phi[q] = (float)st64.phi[q];
+                    if constexpr (IDX) st.idx[q] = st64.idx[q];
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    st.k[i] = st64.k[i];
+                    st.r[i] = st64.r[i];
+                }
+            }
         } else {
             micro<DIM, float, false, ORD, IDX>(s, l0, lmin, A.level_n, st);
         }
