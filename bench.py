@@ -111,8 +111,8 @@ def options(path="fp64"):
     from paper_2103_02388_amd import mmoc
     o = mmoc.mmoc_default_options()
     o.elem_cache = ELEM_CACHE
-    if path == "fp32b":
-        o.eps32_micro = MICRO_BAND
+    if path == "fp32m":
+        o.eps32_micro = 0.0
     return o
 
 
@@ -122,10 +122,11 @@ def log(msg):
 
 
 T0 = time.perf_counter()
-PREC = {"fp64": "MMOC_FP64", "fp32": "MMOC_FP32_MIXED", "fp32f": "MMOC_FP32_FIELDS", "fp32b": "MMOC_FP32_MIXED"}
-NAMES = {"fp64": "fp64", "fp32": "fp32_mixed", "fp32f": "fp32_fields", "fp32b": "fp32_mixed_micro_band"}
-ERR_BOUND = {"fp64": 1e-12, "fp32": 1e-5, "fp32f": 1e-6, "fp32b": 1e-5}
-MICRO_BAND = 2.0 ** -18  # eps32_micro of the "fp32b" leg: the float32-mixed tracer with the micro tie band on
+# "fp32" is the float32-mixed tracer with its default tie bands (macro and
+# micro faces); "fp32m" the same with the micro band off (eps32_micro = 0)
+PREC = {"fp64": "MMOC_FP64", "fp32": "MMOC_FP32_MIXED", "fp32f": "MMOC_FP32_FIELDS", "fp32m": "MMOC_FP32_MIXED"}
+NAMES = {"fp64": "fp64", "fp32": "fp32_mixed", "fp32f": "fp32_fields", "fp32m": "fp32_mixed_macro_band_only"}
+ERR_BOUND = {"fp64": 1e-12, "fp32": 1e-5, "fp32f": 1e-6, "fp32m": 1e-5}
 
 
 def main():
@@ -136,7 +137,7 @@ def main():
     ap.add_argument("--substeps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--paths", default="fp64,fp32,fp32b,fp32f",
+    ap.add_argument("--paths", default="fp64,fp32,fp32m,fp32f",
                     help="tracer paths timed on the shell and the swirl (fp64 is the headline)")
     ap.add_argument("--no-swirl", action="store_true")
     ap.add_argument("--no-diffusion", action="store_true")
@@ -188,7 +189,7 @@ def main():
         print(json.dumps({"surrogate": time_surrogate(S, {})}), flush=True)
         return
     if args.plume_only:
-        paths = [p for p in args.paths.split(",") if p in ("fp64", "fp32", "fp32f")]
+        paths = [p for p in args.paths.split(",") if p in PREC]
         print(json.dumps({"plume3d": time_large(W.plume3d(), 120, paths)}), flush=True)
         return
     paths = args.paths.split(",")
@@ -275,7 +276,7 @@ def main():
         out["surrogate"] = time_surrogate(S, swirl)
     if not args.no_plume:
         log("plume3d")
-        out["plume3d"] = time_large(W.plume3d(), 120, ("fp64", "fp32", "fp32f"))
+        out["plume3d"] = time_large(W.plume3d(), 120, ("fp64", "fp32", "fp32m", "fp32f"))
     if not args.no_diffusion:
         log("diffusion")
         out["diffusion"] = time_diffusion()
@@ -365,7 +366,7 @@ def time_shell(wl, paths, S, steps, warmup, oracle=True):
         entry = {"value": N / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": kern,
                  "trace_only_particles_per_s": N / (kern * 1e-3), "error_bound_vs_oracle": ERR_BOUND[path],
                  "stats": st}
-        if path in ("fp32", "fp32b"):
+        if path in ("fp32", "fp32m"):
             entry["tieband_fraction"] = st["n_tieband"] / max(1, st["n_particles"])
         out[path] = entry
         log("shell: %s %.3f ms per step, trace %.3f ms" % (path, ms, kern))
@@ -611,11 +612,9 @@ def time_large(wl, step, paths, reps=3):
     import torch
     from paper_2103_02388_amd import mmoc
 
-    prec = {"fp64": mmoc.MMOC_FP64, "fp32": mmoc.MMOC_FP32_MIXED, "fp32f": mmoc.MMOC_FP32_FIELDS}
-    names = {"fp64": "fp64", "fp32": "fp32_mixed", "fp32f": "fp32_fields"}
     out = {"workload": wl.description, "level": wl.level}
     for path in paths:
-        tr = mmoc.Tracer.from_workload(wl, precision=prec[path])
+        tr = mmoc.Tracer.from_workload(wl, precision=getattr(mmoc, PREC[path]), options=options(path))
         xt = tr.dof_coords().t().contiguous()
         t_n = step * wl.dt
         if wl.stationary:
@@ -638,13 +637,13 @@ def time_large(wl, step, paths, reps=3):
         ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
         out["particles"] = tr.N
         nb = tr.N * bytes_per_particle(wl.dim, 1 if wl.stationary else 2, 8 if path == "fp64" else 4)
-        out[names[path]] = {"kernel_ms": ms, "trace_only_particles_per_s": tr.N / (ms * 1e-3),
+        out[NAMES[path]] = {"kernel_ms": ms, "trace_only_particles_per_s": tr.N / (ms * 1e-3),
                             "algorithmic_bytes": nb, "hbm_GBps_algorithmic": nb / (ms * 1e-3) / 1e9}
         tr.close()
         del chat, X
         torch.cuda.empty_cache()
     if "fp64" in out:
-        for k in ("fp32_mixed", "fp32_fields"):
+        for k in ("fp32_mixed", "fp32_mixed_macro_band_only", "fp32_fields"):
             if k in out:
                 out[k]["speedup_vs_fp64"] = out["fp64"]["kernel_ms"] / out[k]["kernel_ms"]
     return out

@@ -83,12 +83,12 @@ typedef struct {
     double eps_in;     /* macro acceptance: min barycentric >= -eps_in (default 1e-12) */
     float eps32_macro; /* FP32 path: macro decisions with |min lambda| < eps redone in FP64 (4e-6) */
     float eps32_micro; /* FP32 path: micro decisions with a sorted-coordinate gap < eps*n
-                          redone in FP64 (default 0: off.  The P2 field is continuous
-                          across micro faces, so a micro tie changes the value only by
-                          rounding; particles of a slow flow sit within float32
-                          rounding of a lattice node at every stage and would all be
-                          re-located.  Float32 rounding of the lattice coordinates
-                          is about n * 1e-6; 2^-18 is a sound non-zero band) */
+                          redone in FP64 (default 2^-18: float32 rounding of the
+                          lattice coordinates is about n * 1e-6).  0 turns the micro
+                          band off: the P2 field is continuous across micro faces, so
+                          a micro tie changes the value only by rounding, and
+                          particles of a slow flow, which sit within float32 rounding
+                          of a lattice node at every stage, are then not re-decided */
     int max_hops;      /* walk hops before brute-force location (default 64) */
     int order;         /* element order of the fields and DoFs: 2 = P2 (default; 0 also
                           means 2), 1 = P1, the micro vertices (Sec. 3.1: P1 and P2

@@ -202,7 +202,7 @@ void mmoc_default_options(mmoc_options* o)
     std::memset(o, 0, sizeof *o);
     o->eps_in = 1e-12;
     o->eps32_macro = 4e-6f;
-    o->eps32_micro = 0.0f;  // micro ties are value-neutral (P2 is continuous across micro faces)
+    o->eps32_micro = 0x1p-18f;  // float64 tie-break at micro faces too (0 turns it off)
     o->max_hops = 64;
     o->order = 2;
     o->elem_cache = 1;

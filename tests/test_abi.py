@@ -33,6 +33,8 @@ def test_default_options_and_param_count():
     o = mmoc.mmoc_default_options()
     assert o.eps_in == 1e-12 and o.max_hops == 64
     assert o.elem_cache == 1 and o.keep_chat == 0
+    # float32-mixed: float64 tie-break within a band of both macro and micro faces
+    assert o.eps32_macro == pytest.approx(4e-6, rel=1e-6) and o.eps32_micro == 2.0 ** -18
     assert mmoc.mmoc_mlp_nparams() == 4 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * 3 + 3
 
 

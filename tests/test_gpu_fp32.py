@@ -69,8 +69,10 @@ def test_swirl3d_full_size_fp32(step, S):
     ex, ec = check(p, ch, X, chr_, Xr, lipschitz(p))
     st = p.tr.stats()
     assert st["n_particles"] == p.tr.N and st["n_nan"] == 0
-    # the float64 tie-break (macro band) touches a small fraction of the particles
-    assert st["n_tieband"] < 0.2 * p.tr.N
+    # the float64 tie-break touches a minority of the particles: the macro
+    # band those near the interior faces, the micro band those near a tie of
+    # their micro element (at rest on a lattice node, or slow near one)
+    assert st["n_tieband"] < 0.5 * p.tr.N
     print("fp32 swirl step %d S=%d: X %.2e chat %.2e tieband %.3f" % (step, S, ex, ec, st["n_tieband"] / p.tr.N))
 
 
@@ -94,15 +96,16 @@ def test_small_meshes_and_large_steps_fp32():
 
 
 def test_tie_band_widths():
-    """No band, the default band and a band that sends every location to
-    float64 all stay within tolerance; the wide band matches float64 closely.
+    """No band, the macro band alone, the default bands (macro and micro)
+    and a band that sends every location to float64 all stay within
+    tolerance; the wide band matches float64 closely.
     Every particle locates its stage points after the first (particles at
     rest too: the swirl vanishes on the cube's faces, and their P2 sums at
     their own node stay exactly zero, so they do not move), so the wide band
     counts every particle."""
     wl = W.swirl3d()
     res = {}
-    for name, em, eu in (("none", 0.0, 0.0), ("default", None, None), ("micro", 4e-6, 2.0 ** -18),
+    for name, em, eu in (("none", 0.0, 0.0), ("macro", 4e-6, 0.0), ("default", None, None),
                          ("all", 1e9, 1e9)):
         opt = mmoc.mmoc_default_options()
         if em is not None:
@@ -117,7 +120,7 @@ def test_tie_band_widths():
         res[name] = (ex, p.tr.stats()["n_tieband"])
         at_rest = int((X == p.xg.cpu().numpy()).all(axis=0).sum())
     assert res["none"][1] == 0
-    assert res["micro"][1] > res["default"][1]
+    assert res["default"][1] > res["macro"][1]
     assert 0 < at_rest < p.tr.N // 4
     assert res["all"][1] == p.tr.N
 
